@@ -1,0 +1,784 @@
+/*
+ * Exact CPU oracle for the sample Tukey depth count  n * D_n(z).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may call, link or
+ * load this file; only tests, the smoke check and the CPU-baseline leg of the
+ * benchmark use it.  It shares no code with the HIP path.
+ *
+ * What it computes (Section 1, sample depth, equation HDSV): for observations
+ * X_1..X_n in R^p and a query z,
+ *     d(z) = min over unit u of #{ i : u'(X_i - z) <= 0 },
+ * the depth count (closed halfspaces).  The paper's first algorithm
+ * (Section 3, Algorithm 1 with Algorithm 2 as its bivariate step, justified by
+ * Proposition 1 with r = p-2, equation HDSp22) is followed step by step:
+ *
+ *   shift to z = 0 (Section 2), drop the observations equal to z (they lie on
+ *   every hyperplane and count n0 for every u);
+ *   for every (p-2)-subset I of the rest (Algorithm 1, Step 1):
+ *     (a) a basis of the 2-D complement of span(x_I),
+ *     (b) the bivariate depth of the projected points by one angular sort and
+ *         one circular sweep (Algorithm 2),
+ *     (c) keep the minimum;
+ *   return n0 + minimum (the count form of Algorithm 1, Step 2).
+ *
+ * Readings taken where the paper assumes general position (it suggests a
+ * perturbation instead; here the exact count of the given doubles is the
+ * target, so no perturbation is applied):
+ *   - the complement coordinates are the exact Pluecker coordinates
+ *       phi(x) = (det[x_I | x | e_j], det[x_I | x | e_k])
+ *     for a row pair (j,k) with det[x_I | e_j | e_k] != 0; they are an
+ *     invertible linear image of the orthonormal coordinates of Algorithm 1
+ *     Step 1(a)-(b), so the sweep result is the same;
+ *   - points with phi(x) = 0 are the points inside span(x_I) (Algorithm 2,
+ *     Step 1(a) drops them); instead of the literal correction (p-2), the
+ *     depth delta_I of 0 among those points inside span(x_I) is added, which
+ *     equals 0 whenever span(x_I) holds only the subset itself;
+ *   - points are folded into the half-plane {h1 > 0} U {h1 = 0, h2 > 0}
+ *     instead of using theta = -y1/y2, which is undefined for y2 = 0
+ *     (Algorithm 2, Step 1(b)-(c));
+ *   - the running count is compared only at the end of each run of exactly
+ *     equal angles (Algorithm 2, Step 1(e));
+ *   - subsets whose points are linearly dependent have no 2-D complement and
+ *     are skipped; if the centred data span fewer than p dimensions they are
+ *     first mapped injectively into their span.
+ *
+ * Arithmetic: each predicate (a sign of an integer determinant) is first
+ * evaluated in float64 together with a rigorous bound on its rounding error
+ * (the sum of absolute values of the same expression times gamma_N, N the
+ * number of roundings on any path, input rounding included); when the bound
+ * does not settle the sign, it is recomputed exactly with arbitrary-precision
+ * integers from the exactly integerised inputs (every finite double is an
+ * integer multiple of 2^E for the smallest exponent E present).
+ * With ORACLE_EXACT_ONLY every predicate is computed exactly.
+ */
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+// ------------------------------------------------------------ big integers
+struct Big {
+    int sgn = 0;                 // -1, 0, +1
+    std::vector<uint32_t> mag;   // little-endian magnitude, no leading zeros
+
+    static Big from_u64(uint64_t v, int s = 1) {
+        Big b;
+        if (v == 0) return b;
+        b.sgn = s;
+        b.mag.push_back((uint32_t)v);
+        if (v >> 32) b.mag.push_back((uint32_t)(v >> 32));
+        return b;
+    }
+    static Big from_i64(int64_t v) {
+        if (v < 0) return from_u64((uint64_t)(-(v + 1)) + 1u, -1);
+        return from_u64((uint64_t)v, 1);
+    }
+    bool zero() const { return sgn == 0; }
+};
+
+void trim(std::vector<uint32_t>& m) {
+    while (!m.empty() && m.back() == 0) m.pop_back();
+}
+
+int cmp_mag(const std::vector<uint32_t>& a, const std::vector<uint32_t>& b) {
+    if (a.size() != b.size()) return a.size() < b.size() ? -1 : 1;
+    for (size_t i = a.size(); i-- > 0;) {
+        if (a[i] != b[i]) return a[i] < b[i] ? -1 : 1;
+    }
+    return 0;
+}
+
+std::vector<uint32_t> add_mag(const std::vector<uint32_t>& a, const std::vector<uint32_t>& b) {
+    std::vector<uint32_t> r(std::max(a.size(), b.size()) + 1, 0);
+    uint64_t c = 0;
+    for (size_t i = 0; i < r.size(); ++i) {
+        uint64_t s = c;
+        if (i < a.size()) s += a[i];
+        if (i < b.size()) s += b[i];
+        r[i] = (uint32_t)s;
+        c = s >> 32;
+    }
+    trim(r);
+    return r;
+}
+
+// a - b with |a| >= |b|
+std::vector<uint32_t> sub_mag(const std::vector<uint32_t>& a, const std::vector<uint32_t>& b) {
+    std::vector<uint32_t> r(a.size(), 0);
+    int64_t br = 0;
+    for (size_t i = 0; i < a.size(); ++i) {
+        int64_t s = (int64_t)a[i] - br - (i < b.size() ? (int64_t)b[i] : 0);
+        if (s < 0) { s += ((int64_t)1 << 32); br = 1; } else br = 0;
+        r[i] = (uint32_t)s;
+    }
+    trim(r);
+    return r;
+}
+
+Big add(const Big& a, const Big& b) {
+    if (a.zero()) return b;
+    if (b.zero()) return a;
+    Big r;
+    if (a.sgn == b.sgn) {
+        r.mag = add_mag(a.mag, b.mag);
+        r.sgn = a.sgn;
+        return r;
+    }
+    int c = cmp_mag(a.mag, b.mag);
+    if (c == 0) return r;
+    if (c > 0) { r.mag = sub_mag(a.mag, b.mag); r.sgn = a.sgn; }
+    else       { r.mag = sub_mag(b.mag, a.mag); r.sgn = b.sgn; }
+    return r;
+}
+
+Big neg(Big a) { a.sgn = -a.sgn; return a; }
+Big sub(const Big& a, const Big& b) { return add(a, neg(b)); }
+
+Big mul(const Big& a, const Big& b) {
+    Big r;
+    if (a.zero() || b.zero()) return r;
+    std::vector<uint64_t> acc(a.mag.size() + b.mag.size() + 1, 0);
+    for (size_t i = 0; i < a.mag.size(); ++i) {
+        uint64_t carry = 0;
+        for (size_t j = 0; j < b.mag.size(); ++j) {
+            uint64_t t = (uint64_t)a.mag[i] * b.mag[j] + (acc[i + j] & 0xffffffffu) + carry;
+            acc[i + j] = t & 0xffffffffu;
+            carry = t >> 32;
+        }
+        size_t k = i + b.mag.size();
+        while (carry) {
+            uint64_t t = acc[k] + carry;
+            acc[k] = t & 0xffffffffu;
+            carry = t >> 32;
+            ++k;
+        }
+    }
+    r.mag.resize(acc.size());
+    for (size_t i = 0; i < acc.size(); ++i) r.mag[i] = (uint32_t)acc[i];
+    trim(r.mag);
+    r.sgn = r.mag.empty() ? 0 : a.sgn * b.sgn;
+    return r;
+}
+
+Big shl(const Big& a, int s) {
+    if (a.zero() || s == 0) return a;
+    Big r;
+    r.sgn = a.sgn;
+    int w = s / 32, bits = s % 32;
+    r.mag.assign(a.mag.size() + w + 1, 0);
+    for (size_t i = 0; i < a.mag.size(); ++i) {
+        uint64_t v = (uint64_t)a.mag[i] << bits;
+        r.mag[i + w] |= (uint32_t)v;
+        r.mag[i + w + 1] |= (uint32_t)(v >> 32);
+    }
+    trim(r.mag);
+    return r;
+}
+
+// ----------------------------------------------------- exact integerisation
+// Exponent of the lowest set bit of a finite nonzero double.
+int low_exponent(double v) {
+    int e;
+    double f = std::frexp(std::fabs(v), &e);           // v = f * 2^e, f in [0.5,1)
+    uint64_t M = (uint64_t)std::ldexp(f, 53);           // exact 53-bit integer
+    int tz = __builtin_ctzll(M);
+    return e - 53 + tz;
+}
+
+// v * 2^-E as an exact integer (v must be a multiple of 2^E).
+Big scaled(double v, int E) {
+    if (v == 0.0) return Big();
+    int e;
+    double f = std::frexp(std::fabs(v), &e);
+    uint64_t M = (uint64_t)std::ldexp(f, 53);
+    int sh = e - 53 - E;
+    while (sh < 0) { M >>= 1; ++sh; }                   // drops only zero bits
+    Big b = Big::from_u64(M, v < 0 ? -1 : 1);
+    return shl(b, sh);
+}
+
+// ------------------------------------------------------------- determinants
+const double U64 = std::ldexp(1.0, -53);
+
+// Laplace expansion along the last column (zero entries skipped).
+// Returns the value; *abs_out receives the same expression over |entries|.
+double det_fp(const std::vector<double>& M, int s, double* abs_out) {
+    if (s == 0) { *abs_out = 1.0; return 1.0; }
+    if (s == 1) { *abs_out = std::fabs(M[0]); return M[0]; }
+    double val = 0.0, ab = 0.0;
+    std::vector<double> sub((s - 1) * (s - 1));
+    for (int i = 0; i < s; ++i) {
+        double a = M[i * s + (s - 1)];
+        if (a == 0.0) continue;
+        int r = 0;
+        for (int ii = 0; ii < s; ++ii) {
+            if (ii == i) continue;
+            for (int jj = 0; jj < s - 1; ++jj) sub[r * (s - 1) + jj] = M[ii * s + jj];
+            ++r;
+        }
+        double sa;
+        double sv = det_fp(sub, s - 1, &sa);
+        double sign = ((i + s - 1) % 2 == 0) ? 1.0 : -1.0;
+        val += sign * a * sv;
+        ab += std::fabs(a) * sa;
+    }
+    *abs_out = ab;
+    return val;
+}
+
+// Error bound for det_fp on an s x s matrix whose entries carry at most one
+// relative rounding each.  Every monomial passes through at most s input
+// roundings, s-1 products and, per level, at most s additions.
+double det_bound(double absval, int s) {
+    double N = (double)(s * s + 3 * s + 4);
+    return absval * (N * U64) / (1.0 - N * U64) * 1.0001;
+}
+
+Big det_big(const std::vector<Big>& M, int s) {
+    if (s == 0) return Big::from_i64(1);
+    if (s == 1) return M[0];
+    Big val;
+    std::vector<Big> sub((s - 1) * (s - 1));
+    for (int i = 0; i < s; ++i) {
+        const Big& a = M[i * s + (s - 1)];
+        if (a.zero()) continue;
+        int r = 0;
+        for (int ii = 0; ii < s; ++ii) {
+            if (ii == i) continue;
+            for (int jj = 0; jj < s - 1; ++jj) sub[r * (s - 1) + jj] = M[ii * s + jj];
+            ++r;
+        }
+        Big t = mul(a, det_big(sub, s - 1));
+        if ((i + s - 1) % 2 != 0) t = neg(t);
+        val = add(val, t);
+    }
+    return val;
+}
+
+Big dot_big(const std::vector<Big>& g, const Big* x, int p) {
+    Big s;
+    for (int i = 0; i < p; ++i) s = add(s, mul(g[i], x[i]));
+    return s;
+}
+
+// ------------------------------------------------------------ point sets
+struct PointSet {
+    int p = 0;
+    int n = 0;
+    std::vector<Big> xi;     // n*p exact integers
+    std::vector<double> xd;  // n*p rounded values (relative error <= u)
+    const Big* ex(int i) const { return &xi[(size_t)i * p]; }
+    const double* fd(int i) const { return &xd[(size_t)i * p]; }
+};
+
+// Is the s-minor of the (p x cols) column set on the given rows nonzero?
+// cols: indices into P.  Exact unless the float64 filter settles it.
+int minor_sign(const PointSet& P, const std::vector<int>& cols, const std::vector<int>& rows,
+               bool exact_only) {
+    int s = (int)cols.size();
+    if (!exact_only) {
+        std::vector<double> M(s * s);
+        for (int r = 0; r < s; ++r)
+            for (int c = 0; c < s; ++c) M[r * s + c] = P.fd(cols[c])[rows[r]];
+        double ab;
+        double v = det_fp(M, s, &ab);
+        if (std::fabs(v) > det_bound(ab, s)) return v > 0 ? 1 : -1;
+    }
+    std::vector<Big> M(s * s);
+    for (int r = 0; r < s; ++r)
+        for (int c = 0; c < s; ++c) M[r * s + c] = P.ex(cols[c])[rows[r]];
+    return det_big(M, s).sgn;
+}
+
+bool next_comb(std::vector<int>& c, int n) {
+    int k = (int)c.size();
+    for (int i = k - 1; i >= 0; --i) {
+        if (c[i] < n - k + i) {
+            ++c[i];
+            for (int j = i + 1; j < k; ++j) c[j] = c[j - 1] + 1;
+            return true;
+        }
+    }
+    return false;
+}
+
+// Rank of the columns `idx` of P, and rows giving a nonzero maximal minor.
+int rank_of(const PointSet& P, const std::vector<int>& idx, std::vector<int>* basis_rows,
+            bool exact_only) {
+    std::vector<int> basis;
+    for (int v : idx) {
+        if ((int)basis.size() == P.p) break;
+        std::vector<int> cols = basis;
+        cols.push_back(v);
+        int s = (int)cols.size();
+        std::vector<int> rows(s);
+        for (int i = 0; i < s; ++i) rows[i] = i;
+        bool indep = false;
+        do {
+            if (minor_sign(P, cols, rows, exact_only) != 0) { indep = true; break; }
+        } while (next_comb(rows, P.p));
+        if (indep) basis.push_back(v);
+    }
+    if (basis_rows) {
+        int s = (int)basis.size();
+        std::vector<int> rows(s);
+        for (int i = 0; i < s; ++i) rows[i] = i;
+        basis_rows->clear();
+        if (s == 0) return 0;
+        do {
+            if (minor_sign(P, basis, rows, exact_only) != 0) { *basis_rows = rows; break; }
+        } while (next_comb(rows, P.p));
+    }
+    return (int)basis.size();
+}
+
+PointSet restrict_rows(const PointSet& P, const std::vector<int>& idx, const std::vector<int>& rows) {
+    PointSet Q;
+    Q.p = (int)rows.size();
+    Q.n = (int)idx.size();
+    Q.xi.resize((size_t)Q.n * Q.p);
+    Q.xd.resize((size_t)Q.n * Q.p);
+    for (int i = 0; i < Q.n; ++i)
+        for (int r = 0; r < Q.p; ++r) {
+            Q.xi[(size_t)i * Q.p + r] = P.ex(idx[i])[rows[r]];
+            Q.xd[(size_t)i * Q.p + r] = P.fd(idx[i])[rows[r]];
+        }
+    return Q;
+}
+
+// ---------------------------------------------------- small exact depth
+// min over generic u of #{ v : u'v < 0 } for nonzero integer vectors, by the
+// critical-direction route (equation DNPp1): every optimal open cone has an
+// extreme ray normal to d-1 independent points; near that ray the count is
+// the strict count plus the depth of the points on the hyperplane.
+int small_depth(const PointSet& V) {
+    if (V.n == 0) return 0;
+    std::vector<int> all(V.n);
+    for (int i = 0; i < V.n; ++i) all[i] = i;
+    std::vector<int> rows;
+    int rho = rank_of(V, all, &rows, true);
+    if (rho < V.p) return small_depth(restrict_rows(V, all, rows));
+    int d = V.p;
+    if (d == 1) {
+        int pos = 0, neg = 0;
+        for (int i = 0; i < V.n; ++i) (V.ex(i)[0].sgn > 0 ? pos : neg)++;
+        return std::min(pos, neg);
+    }
+    int best = V.n;
+    std::vector<int> J(d - 1);
+    for (int i = 0; i < d - 1; ++i) J[i] = i;
+    if (V.n < d - 1) return 0;
+    do {
+        // generalised cross product u_i = det[v_J | e_i]
+        std::vector<Big> u(d);
+        bool nz = false;
+        for (int i = 0; i < d; ++i) {
+            std::vector<Big> M(d * d);
+            for (int r = 0; r < d; ++r) {
+                for (int c = 0; c < d - 1; ++c) M[r * d + c] = V.ex(J[c])[r];
+                M[r * d + (d - 1)] = Big::from_i64(r == i ? 1 : 0);
+            }
+            u[i] = det_big(M, d);
+            if (!u[i].zero()) nz = true;
+        }
+        if (!nz) continue;
+        int pos = 0, neg = 0, drop = -1;
+        for (int i = 0; i < d; ++i) if (!u[i].zero()) { drop = i; break; }
+        std::vector<int> on;
+        for (int l = 0; l < V.n; ++l) {
+            int s = dot_big(u, V.ex(l), d).sgn;
+            if (s > 0) ++pos; else if (s < 0) ++neg; else on.push_back(l);
+        }
+        std::vector<int> keep;
+        for (int r = 0; r < d; ++r) if (r != drop) keep.push_back(r);
+        int rec = small_depth(restrict_rows(V, on, keep));
+        best = std::min(best, std::min(pos, neg) + rec);
+    } while (next_comb(J, V.n));
+    return best;
+}
+
+// ------------------------------------------------- per-subset computation
+struct Ctx {
+    const PointSet* P;
+    bool exact_only;
+};
+
+// Returns delta_I + b_I for the subset `I`, or -1 if the subset is invalid.
+int subset_term(const Ctx& C, const std::vector<int>& I) {
+    const PointSet& P = *C.P;
+    const int p = P.p, k = p - 2;
+    const bool xo = C.exact_only;
+
+    // ---- row pair (j,kk) with omega = det[x_I | e_j | e_kk] != 0
+    auto build_unit = [&](int a, int b, std::vector<double>* Md, std::vector<Big>* Mb) {
+        // p x p matrix [x_I | e_a | e_b]
+        if (Md) {
+            Md->assign(p * p, 0.0);
+            for (int r = 0; r < p; ++r) {
+                for (int c = 0; c < k; ++c) (*Md)[r * p + c] = P.fd(I[c])[r];
+                (*Md)[r * p + k] = (r == a) ? 1.0 : 0.0;
+                (*Md)[r * p + k + 1] = (r == b) ? 1.0 : 0.0;
+            }
+        }
+        if (Mb) {
+            Mb->assign(p * p, Big());
+            for (int r = 0; r < p; ++r) {
+                for (int c = 0; c < k; ++c) (*Mb)[r * p + c] = P.ex(I[c])[r];
+                (*Mb)[r * p + k] = Big::from_i64(r == a ? 1 : 0);
+                (*Mb)[r * p + k + 1] = Big::from_i64(r == b ? 1 : 0);
+            }
+        }
+    };
+    int J = -1, K = -1;
+    {
+        double bestv = -1.0;
+        std::vector<double> Md;
+        std::vector<std::pair<double, std::pair<int, int>>> cand;
+        for (int a = 0; a < p; ++a)
+            for (int b = a + 1; b < p; ++b) {
+                build_unit(a, b, &Md, nullptr);
+                double ab;
+                double v = det_fp(Md, p, &ab);
+                cand.push_back({std::fabs(v), {a, b}});
+                if (!xo && std::fabs(v) > det_bound(ab, p) && std::fabs(v) > bestv) {
+                    bestv = std::fabs(v);
+                    J = a; K = b;
+                }
+            }
+        if (J < 0) {
+            std::sort(cand.begin(), cand.end(), [](auto& x, auto& y) { return x.first > y.first; });
+            std::vector<Big> Mb;
+            for (auto& c : cand) {
+                build_unit(c.second.first, c.second.second, nullptr, &Mb);
+                if (!det_big(Mb, p).zero()) { J = c.second.first; K = c.second.second; break; }
+            }
+        }
+        if (J < 0) return -1;   // x_I linearly dependent: no 2-D complement
+    }
+
+    // ---- Pluecker rows g1_i = det[x_I | e_i | e_J], g2_i = det[x_I | e_i | e_K]
+    std::vector<double> g1(p), g2(p), E1(p), E2(p);
+    {
+        std::vector<double> Md;
+        for (int i = 0; i < p; ++i) {
+            double ab;
+            build_unit(i, J, &Md, nullptr);
+            g1[i] = det_fp(Md, p, &ab);
+            E1[i] = det_bound(ab, p);
+            build_unit(i, K, &Md, nullptr);
+            g2[i] = det_fp(Md, p, &ab);
+            E2[i] = det_bound(ab, p);
+        }
+    }
+    std::vector<Big> G1, G2;     // exact rows, computed on first need
+    auto need_exact_rows = [&]() {
+        if (!G1.empty()) return;
+        G1.resize(p); G2.resize(p);
+        std::vector<Big> Mb;
+        for (int i = 0; i < p; ++i) {
+            build_unit(i, J, nullptr, &Mb);
+            G1[i] = det_big(Mb, p);
+            build_unit(i, K, nullptr, &Mb);
+            G2[i] = det_big(Mb, p);
+        }
+    };
+
+    std::vector<char> inI(P.n, 0);
+    for (int v : I) inI[v] = 1;
+
+    struct Pt {
+        int idx;
+        int sig;          // fold sign
+        double h1, h2;    // folded float64 coordinates
+        double e;         // absolute error bound on h1 and h2
+        bool have_exact;
+        Big H1, H2;       // folded exact coordinates (if computed)
+    };
+    std::vector<Pt> pts;
+    pts.reserve(P.n);
+    std::vector<int> inspan;   // K_I \ I
+    const double gam = (double)(p + 3) * U64 * 1.0001;
+    for (int l = 0; l < P.n; ++l) {
+        if (inI[l]) continue;
+        const double* x = P.fd(l);
+        double y1 = 0, y2 = 0, a1 = 0, a2 = 0, b1 = 0, b2 = 0;
+        for (int i = 0; i < p; ++i) {
+            y1 += g1[i] * x[i];
+            y2 += g2[i] * x[i];
+            a1 += std::fabs(g1[i] * x[i]);
+            a2 += std::fabs(g2[i] * x[i]);
+            b1 += E1[i] * std::fabs(x[i]);
+            b2 += E2[i] * std::fabs(x[i]);
+        }
+        double e1 = (b1 * (1 + 2 * U64) + gam * a1) * 1.0001;
+        double e2 = (b2 * (1 + 2 * U64) + gam * a2) * 1.0001;
+        double e = std::max(e1, e2);
+        Pt q;
+        q.idx = l;
+        q.e = e;
+        q.have_exact = false;
+        int s1 = (!xo && std::fabs(y1) > e1) ? (y1 > 0 ? 1 : -1) : 2;   // 2 = unknown
+        if (s1 == 2) {
+            need_exact_rows();
+            Big Y1 = dot_big(G1, P.ex(l), p);
+            Big Y2 = dot_big(G2, P.ex(l), p);
+            if (Y1.zero() && Y2.zero()) { inspan.push_back(l); continue; }
+            q.sig = Y1.zero() ? Y2.sgn : Y1.sgn;
+            q.have_exact = true;
+            q.H1 = q.sig > 0 ? Y1 : neg(Y1);
+            q.H2 = q.sig > 0 ? Y2 : neg(Y2);
+        } else {
+            q.sig = s1;
+        }
+        q.h1 = q.sig * y1;
+        q.h2 = q.sig * y2;
+        pts.push_back(std::move(q));
+    }
+
+    auto exact_of = [&](Pt& q) {
+        if (q.have_exact) return;
+        need_exact_rows();
+        Big Y1 = dot_big(G1, P.ex(q.idx), p);
+        Big Y2 = dot_big(G2, P.ex(q.idx), p);
+        q.H1 = q.sig > 0 ? Y1 : neg(Y1);
+        q.H2 = q.sig > 0 ? Y2 : neg(Y2);
+        q.have_exact = true;
+    };
+    // orientation of the folded pair: sign of cross(h_a, h_b)
+    auto orient = [&](Pt& a, Pt& b) -> int {
+        if (!xo) {
+            double c = a.h1 * b.h2 - a.h2 * b.h1;
+            double bound = a.e * (std::fabs(b.h1) + std::fabs(b.h2)) + b.e * (std::fabs(a.h1) + std::fabs(a.h2))
+                         + 2.0 * a.e * b.e + 3.0 * U64 * (std::fabs(a.h1 * b.h2) + std::fabs(a.h2 * b.h1));
+            bound *= 1.0001;
+            if (std::fabs(c) > bound) return c > 0 ? 1 : -1;
+        }
+        exact_of(a);
+        exact_of(b);
+        return sub(mul(a.H1, b.H2), mul(a.H2, b.H1)).sgn;
+    };
+
+    // Angular order of the folded points (Algorithm 2, Step 1(e)).  A float64
+    // angle gives a candidate order; it is accepted only if every adjacent
+    // pair is confirmed non-decreasing by the exact orientation predicate,
+    // which for a total preorder proves the whole order.  Otherwise the points
+    // are sorted again with the exact predicate as comparator.
+    std::vector<int> order(pts.size());
+    for (size_t i = 0; i < pts.size(); ++i) order[i] = (int)i;
+    std::vector<double> ang(pts.size());
+    for (size_t i = 0; i < pts.size(); ++i) ang[i] = std::atan2(pts[i].h2, pts[i].h1);
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return ang[a] < ang[b]; });
+    std::vector<int> adj(order.empty() ? 0 : order.size() - 1);
+    bool ok = true;
+    for (size_t i = 0; i + 1 < order.size(); ++i) {
+        adj[i] = orient(pts[order[i]], pts[order[i + 1]]);
+        if (adj[i] < 0) { ok = false; break; }
+    }
+    if (!ok) {
+        std::sort(order.begin(), order.end(), [&](int a, int b) { return orient(pts[a], pts[b]) > 0; });
+        for (size_t i = 0; i + 1 < order.size(); ++i) adj[i] = orient(pts[order[i]], pts[order[i + 1]]);
+    }
+
+    // ---- circular sweep with grouped ties (Algorithm 2, Step 1(c)-(e))
+    const int m = (int)pts.size();
+    int S = 0;
+    for (auto& q : pts) if (q.sig > 0) ++S;
+    int best = std::min(S, m - S);
+    for (size_t i = 0; i < order.size(); ++i) {
+        S += -pts[order[i]].sig;
+        bool run_end = (i + 1 == order.size()) || adj[i] != 0;
+        if (run_end) best = std::min(best, std::min(S, m - S));
+    }
+
+    // ---- depth of 0 inside span(x_I) among the points lying there
+    int delta = 0;
+    if (!inspan.empty()) {
+        std::vector<int> Kset = I;
+        for (int v : inspan) Kset.push_back(v);
+        std::vector<int> rows(p);
+        for (int r = 0; r < p; ++r) rows[r] = r;
+        delta = small_depth(restrict_rows(P, Kset, rows));
+    }
+    return delta + best;
+}
+
+uint64_t binom(int n, int k) {
+    if (k < 0 || n < k) return 0;
+    uint64_t r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (uint64_t)(n - k + i) / (uint64_t)i;
+    return r;
+}
+
+// lexicographic unranking of k-subsets of {0..n-1}
+void unrank_lex(uint64_t r, int n, int k, std::vector<int>& c) {
+    c.resize(k);
+    int x = 0;
+    for (int i = 0; i < k; ++i) {
+        while (true) {
+            uint64_t b = binom(n - x - 1, k - i - 1);
+            if (r < b) break;
+            r -= b;
+            ++x;
+        }
+        c[i] = x++;
+    }
+}
+
+struct Prepared {
+    int n0 = 0;
+    int kind = 0;   // 0: use subsets, 1: closed form value in `value`
+    int value = 0;
+    PointSet P;     // centred nonzero points, mapped into their span
+};
+
+Prepared prepare(const double* X, int64_t n, int p, const double* z, bool exact_only) {
+    Prepared R;
+    int E = std::numeric_limits<int>::max();
+    for (int64_t i = 0; i < n * p; ++i) if (X[i] != 0.0) E = std::min(E, low_exponent(X[i]));
+    for (int c = 0; c < p; ++c) if (z[c] != 0.0) E = std::min(E, low_exponent(z[c]));
+    if (E == std::numeric_limits<int>::max()) E = 0;
+    PointSet W;
+    W.p = p;
+    std::vector<Big> zi(p);
+    for (int c = 0; c < p; ++c) zi[c] = scaled(z[c], E);
+    for (int64_t i = 0; i < n; ++i) {
+        bool same = true;
+        for (int c = 0; c < p; ++c) if (X[i * p + c] != z[c]) { same = false; break; }
+        if (same) { ++R.n0; continue; }
+        for (int c = 0; c < p; ++c) {
+            W.xi.push_back(sub(scaled(X[i * p + c], E), zi[c]));
+            W.xd.push_back(X[i * p + c] - z[c]);
+        }
+        ++W.n;
+    }
+    if (W.n == 0) { R.kind = 1; R.value = 0; return R; }
+    std::vector<int> all(W.n);
+    for (int i = 0; i < W.n; ++i) all[i] = i;
+    std::vector<int> rows;
+    int rho = rank_of(W, all, &rows, exact_only);
+    PointSet Q = (rho < p) ? restrict_rows(W, all, rows) : W;
+    if (Q.p == 1) {
+        int pos = 0, neg = 0;
+        for (int i = 0; i < Q.n; ++i) (Q.ex(i)[0].sgn > 0 ? pos : neg)++;
+        R.kind = 1;
+        R.value = std::min(pos, neg);
+        return R;
+    }
+    R.P = std::move(Q);
+    return R;
+}
+
+}  // namespace
+
+extern "C" {
+
+enum { ORACLE_EXACT_ONLY = 1 };
+
+// Depth counts of the m queries Z (m x p, row-major) w.r.t. X (n x p).
+// out[q] = n * D_n(Z_q).  threads <= 0: OpenMP default.  Returns 0 on success.
+int oracle_depth(const double* X, int64_t n, int32_t p, const double* Z, int64_t m,
+                 int64_t* out, int32_t threads, int32_t flags) {
+    if (!X || !Z || !out || n < 1 || p < 1 || m < 0) return 1;
+    for (int64_t i = 0; i < n * p; ++i) if (!std::isfinite(X[i])) return 2;
+    for (int64_t i = 0; i < m * p; ++i) if (!std::isfinite(Z[i])) return 2;
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#endif
+    const bool xo = (flags & ORACLE_EXACT_ONLY) != 0;
+    for (int64_t q = 0; q < m; ++q) {
+        Prepared R = prepare(X, n, p, Z + q * p, xo);
+        if (R.kind == 1) { out[q] = R.n0 + R.value; continue; }
+        const int k = R.P.p - 2;
+        const uint64_t total = binom(R.P.n, k);
+        Ctx C{&R.P, xo};
+        int best = std::numeric_limits<int>::max();
+        const uint64_t chunk = 256;
+        const int64_t nchunks = (int64_t)((total + chunk - 1) / chunk);
+#pragma omp parallel for schedule(dynamic, 1) reduction(min : best)
+        for (int64_t ch = 0; ch < nchunks; ++ch) {
+            uint64_t r0 = (uint64_t)ch * chunk, r1 = std::min(total, r0 + chunk);
+            std::vector<int> I;
+            unrank_lex(r0, R.P.n, k, I);
+            for (uint64_t r = r0; r < r1; ++r) {
+                int t = subset_term(C, I);
+                if (t >= 0 && t < best) best = t;
+                if (r + 1 < r1) next_comb(I, R.P.n);
+            }
+        }
+        out[q] = R.n0 + best;   // at least one valid subset exists after the span map
+    }
+    return 0;
+}
+
+// Minimum of delta_I + b_I over the subsets of lexicographic rank [r0, r1)
+// for one query (a bounded sample of the full loop), plus n0.  Only defined
+// when the centred points span R^p.  *swept receives the number of subsets.
+int oracle_depth_range(const double* X, int64_t n, int32_t p, const double* z, uint64_t r0,
+                       uint64_t r1, int64_t* out_min, uint64_t* swept, int32_t threads,
+                       int32_t flags) {
+    if (!X || !z || !out_min || !swept || n < 1 || p < 3) return 1;
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#endif
+    const bool xo = (flags & ORACLE_EXACT_ONLY) != 0;
+    Prepared R = prepare(X, n, p, z, xo);
+    if (R.kind == 1 || R.P.p != p) return 3;
+    const int k = p - 2;
+    const uint64_t total = binom(R.P.n, k);
+    r1 = std::min(r1, total);
+    if (r0 > r1) r0 = r1;
+    Ctx C{&R.P, xo};
+    int best = std::numeric_limits<int>::max();
+    const uint64_t chunk = 256;
+    const int64_t nchunks = (int64_t)((r1 - r0 + chunk - 1) / chunk);
+#pragma omp parallel for schedule(dynamic, 1) reduction(min : best)
+    for (int64_t ch = 0; ch < nchunks; ++ch) {
+        uint64_t a = r0 + (uint64_t)ch * chunk, b = std::min(r1, a + chunk);
+        std::vector<int> I;
+        unrank_lex(a, R.P.n, k, I);
+        for (uint64_t r = a; r < b; ++r) {
+            int t = subset_term(C, I);
+            if (t >= 0 && t < best) best = t;
+            if (r + 1 < b) next_comb(I, R.P.n);
+        }
+    }
+    *out_min = (best == std::numeric_limits<int>::max()) ? -1 : (int64_t)(R.n0 + best);
+    *swept = r1 - r0;
+    return 0;
+}
+
+// Depth count by the critical-direction route alone (equation DNPp1 with the
+// exact recursion for points on the critical hyperplane).  O(n^p): tiny inputs.
+int oracle_depth_vertex(const double* X, int64_t n, int32_t p, const double* z, int64_t* out) {
+    if (!X || !z || !out || n < 1 || p < 1) return 1;
+    int E = std::numeric_limits<int>::max();
+    for (int64_t i = 0; i < n * p; ++i) if (X[i] != 0.0) E = std::min(E, low_exponent(X[i]));
+    for (int c = 0; c < p; ++c) if (z[c] != 0.0) E = std::min(E, low_exponent(z[c]));
+    if (E == std::numeric_limits<int>::max()) E = 0;
+    PointSet W;
+    W.p = p;
+    int n0 = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        bool same = true;
+        for (int c = 0; c < p; ++c) if (X[i * p + c] != z[c]) { same = false; break; }
+        if (same) { ++n0; continue; }
+        for (int c = 0; c < p; ++c) {
+            W.xi.push_back(sub(scaled(X[i * p + c], E), scaled(z[c], E)));
+            W.xd.push_back(X[i * p + c] - z[c]);
+        }
+        ++W.n;
+    }
+    *out = n0 + small_depth(W);
+    return 0;
+}
+
+uint64_t oracle_binom(int32_t n, int32_t k) { return binom(n, k); }
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+"""Write the stored expected depth counts used by the GPU parity tests.
+
+Every value here comes from the CPU oracle (``oracle/``) run on the seeded
+inputs of ``workloads``; nothing is taken from the HIP path.  The script is
+resumable: each finished query is saved at once, and queries already present
+are skipped.
+
+    python tests/golden/make_golden.py [c1 c2 c3 c5 c4] [--threads T]
+
+Files: ``tests/golden/<config>.json`` holding
+``{"config", "seed", "source", "n", "p", "counts": {query_index: count}}``;
+for c4 the counts are keyed ``"<dataset>:<query>"`` and only a seeded
+subsample (queries of datasets whose per-query cost C(n, p-2) * n is at most
+``C4_BUDGET`` point-steps) is stored.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import workloads  # noqa: E402
+
+SEEDS = {"c1": 0, "c2": 2, "c3": 3, "c4": 4, "c5": 5}
+C4_BUDGET = 3.0e8
+
+
+def c4_subsample():
+    """(dataset, query) pairs whose oracle cost fits the budget."""
+    data = workloads.c4()
+    sel = []
+    for d, (X, Z) in enumerate(data):
+        n, p = X.shape
+        cost = math.comb(n, p - 2) * n
+        if cost <= C4_BUDGET:
+            sel.extend((d, q) for q in range(Z.shape[0]))
+    return sel
+
+
+def _load(path):
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return None
+
+
+def _save(path, obj):
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(obj, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def run(cfg: str, threads: int):
+    path = os.path.join(HERE, cfg + ".json")
+    obj = _load(path)
+    if cfg == "c4":
+        data = workloads.c4()
+        if obj is None:
+            obj = {"config": "c4", "seed": SEEDS["c4"], "source": "oracle/td_oracle.cpp",
+                   "subsample_rule": "C(n,p-2)*n <= %g" % C4_BUDGET, "counts": {}}
+        for d, q in c4_subsample():
+            key = "%d:%d" % (d, q)
+            if key in obj["counts"]:
+                continue
+            X, Z = data[d]
+            t = time.time()
+            v = int(oracle.depth_counts(X, Z[q:q + 1], threads=threads)[0])
+            obj["counts"][key] = v
+            _save(path, obj)
+            print("c4 %s -> %d (%.1fs)" % (key, v, time.time() - t), flush=True)
+        return
+    X, Z = workloads.config(cfg)
+    if obj is None:
+        obj = {"config": cfg, "seed": SEEDS[cfg], "source": "oracle/td_oracle.cpp",
+               "n": int(X.shape[0]), "p": int(X.shape[1]), "counts": {}}
+    order = list(range(Z.shape[0]))
+    for q in order:
+        if str(q) in obj["counts"]:
+            continue
+        t = time.time()
+        v = int(oracle.depth_counts(X, Z[q:q + 1], threads=threads)[0])
+        obj["counts"][str(q)] = v
+        _save(path, obj)
+        print("%s q=%d -> %d (%.1fs)" % (cfg, q, v, time.time() - t), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("configs", nargs="*", default=["c1", "c2", "c3", "c5", "c4"])
+    ap.add_argument("--threads", type=int, default=0)
+    a = ap.parse_args()
+    oracle.build(force=False)
+    for cfg in a.configs:
+        run(cfg, a.threads or oracle.default_threads())
+
+
+if __name__ == "__main__":
+    main()
