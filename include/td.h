@@ -1,0 +1,151 @@
+/*
+ * td.h -- C ABI of the exact Tukey-depth library for AMD MI355X (gfx950).
+ *
+ * The library computes depth counts  counts[q] = n * D_n(Z_q),  where
+ *     D_n(z) = min over unit u of  #{ i : u'X_i <= u'z } / n
+ * is the sample Tukey depth (Section 1, equation HDSV), with the paper's
+ * first algorithm (Section 3): the depth of the origin after the shift
+ * x_i = X_i - z equals, by Proposition 1 with r = p-2 (equation HDSp22), the
+ * minimum over all (p-2)-subsets I of the observations of a bivariate depth,
+ * obtained by projecting onto the 2-D complement of span(x_I) (Algorithm 1,
+ * Step 1(a)-(b)) and running one angular sort and one circular sweep
+ * (Algorithm 2); the count form of Algorithm 1, Step 2, is returned.
+ *
+ * The result is an exact integer for every finite input, not only in general
+ * position: points inside span(x_I), exactly equal angles and dependent
+ * subsets are decided with exact integer predicates (TD_PREC_FP32_FILTERED and
+ * TD_PREC_EXACT).  TD_PREC_FP64_PLAIN follows the paper's steps in float64
+ * without certification (ties are grouped only when the float64 keys are
+ * equal, points inside span(x_I) are counted as in Algorithm 2, Step 2) and
+ * can differ from the exact count on degenerate data.
+ *
+ * Conventions for every entry point below.
+ *  - X (n x p) and Z (m x p) are row-major contiguous float64 arrays in
+ *    DEVICE memory; counts (m int32) is DEVICE memory.  All three are owned by
+ *    the caller; the library keeps no reference to them once the enqueued
+ *    work has completed.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls are asynchronous on that stream: results are valid once the stream
+ *    has completed the work.  Calls on the same stream are ordered; the
+ *    library serialises its own workspace between calls.
+ *  - Argument errors are reported synchronously by the return value and leave
+ *    `counts` untouched.  Limits: 1 <= p <= TD_MAX_P, 1 <= n <= TD_MAX_N,
+ *    m >= 0 (m = 0 is a no-op).
+ *  - Data-dependent failures are reported per query: counts[q] = -1 and a bit
+ *    in td_stats.device_status (see TD_DEV_*), readable after the stream has
+ *    completed.
+ *  - The library lazily creates a per-device workspace (device buffers, a
+ *    binomial table, captured graphs); td_release() frees it.
+ */
+#ifndef TD_H
+#define TD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TD_MAX_P 8
+#define TD_MAX_N 1024
+
+typedef enum {
+    TD_OK = 0,
+    TD_ERR_INVALID_ARG = 1,   /* null pointer, size out of range, bad option */
+    TD_ERR_UNSUPPORTED = 2,   /* valid request the library does not handle */
+    TD_ERR_OUT_OF_MEMORY = 3, /* workspace allocation failed */
+    TD_ERR_HIP = 4,           /* a HIP runtime call failed */
+    TD_ERR_DEVICE_STATUS = 5, /* td_get_stats: the last call flagged queries */
+    TD_ERR_NO_DEVICE = 6      /* no HIP device is visible */
+} td_status;
+
+/* Per-query failure bits of td_stats.device_status (OR over the queries). */
+#define TD_DEV_NONFINITE 1        /* NaN or Inf in X or in the query */
+#define TD_DEV_NO_VALID_SUBSET 2  /* the centred points span <= p-3 dimensions */
+#define TD_DEV_DEFER_OVERFLOW 4   /* more uncertain subsets than deferred_capacity */
+#define TD_DEV_EXACT_RANGE 8      /* exact fallback needed but the integerised
+                                     inputs exceed 126 bits */
+#define TD_DEV_DEGENERACY_LIMIT 16/* exact fallback met a tie run or an in-span
+                                     point set larger than the library handles */
+
+typedef enum {
+    TD_PREC_FP64_PLAIN = 0,    /* float64 keys, no certification */
+    TD_PREC_FP32_FILTERED = 1, /* float32 projection with forward error bounds,
+                                  float64 re-check, exact fallback */
+    TD_PREC_EXACT = 2          /* float64 projection with error bounds and
+                                  exact fallback for every subset */
+} td_precision;
+
+typedef struct {
+    int32_t precision;         /* td_precision (default TD_PREC_FP32_FILTERED) */
+    int32_t autotune;          /* 1: use the tuned launch shape when cached */
+    int32_t chunk;             /* subsets per work item (multiple of 64), 0 = auto */
+    int32_t grid_blocks;       /* persistent blocks, 0 = auto */
+    double filter_scale;       /* scales the float32 error radius: 1 normal,
+                                  +inf re-checks every float32 decision,
+                                  0 trusts float32 blindly (negative control,
+                                  results may be wrong) */
+    int32_t force_exact;       /* 1: every subset goes through the exact tier */
+    int32_t timing;            /* 1: record HIP events per stage (td_get_stats) */
+    int64_t deferred_capacity; /* max deferred subsets per call, 0 = default */
+} td_options;
+
+typedef struct {
+    uint64_t subsets_swept;      /* subsets processed by the main kernels */
+    uint64_t fp64_rechecks;      /* float32 decisions re-checked in float64 */
+    uint64_t deferred_subsets;   /* subsets sent to the exact tier */
+    uint64_t exact_predicates;   /* exact integer predicates evaluated */
+    uint64_t degenerate_subsets; /* subsets with extra points inside span(x_I) */
+    uint64_t invalid_subsets;    /* subsets with linearly dependent points */
+    int32_t device_status;       /* OR of TD_DEV_* over the last call's queries */
+    float prep_ms, subset_ms, exact_ms, finalize_ms, total_ms; /* if timing */
+} td_stats;
+
+/* One independent depth problem of a batch (pointers as for td_depth). */
+typedef struct {
+    const double* X;
+    int64_t n;
+    int32_t p;
+    const double* Z;
+    int64_t m;
+    int32_t* counts;
+} td_problem;
+
+/* Fills *out with the defaults. */
+td_status td_default_options(td_options* out);
+
+/* Depth counts of the m queries Z w.r.t. X with the default options. */
+td_status td_depth(const double* X, int64_t n, int32_t p, const double* Z, int64_t m,
+                   int32_t* counts, void* stream);
+
+/* As td_depth with explicit options (NULL = defaults). */
+td_status td_depth_ex(const double* X, int64_t n, int32_t p, const double* Z, int64_t m,
+                      int32_t* counts, const td_options* opt, void* stream);
+
+/* Many independent problems of uneven n and p in one captured HIP graph
+ * launch: one preparation kernel, one persistent subset kernel pulling
+ * (query, subset-range) work items from a device counter, the exact tier and
+ * the finalisation.  `probs` is a HOST array read during the call; the
+ * pointers inside follow the td_depth conventions. */
+td_status td_depth_batched(const td_problem* probs, int32_t num, const td_options* opt,
+                           void* stream);
+
+/* Counters and timings of the last call; synchronises the device. */
+td_status td_get_stats(td_stats* out);
+
+/* Times candidate launch shapes for (p, n) on synthetic data and caches the
+ * fastest for later calls with autotune = 1; synchronises the device. */
+td_status td_autotune(int32_t p, int64_t n, const td_options* base, void* stream);
+
+const char* td_status_string(td_status s);
+
+/* Frees the workspace of every device (safe to call more than once). */
+void td_release(void);
+
+int32_t td_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TD_H */

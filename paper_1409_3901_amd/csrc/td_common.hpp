@@ -1,0 +1,98 @@
+// Internal layouts shared by the host launcher and the kernels.
+#pragma once
+#include <stdint.h>
+
+namespace td {
+
+constexpr int kMaxP = 8;
+constexpr int kMaxN = 1024;
+constexpr int kWave = 64;
+constexpr int kBinomK = 7;             // binomial table columns k = 0..6
+constexpr int kBinomN = kMaxN + 2;     // rows n = 0..kMaxN+1
+
+enum Tier : int { kPlain = 0, kFilt = 1, kExact = 2 };
+
+// Query status bits (match TD_DEV_* of td.h).
+constexpr int kStNonfinite = 1;
+constexpr int kStNoValid = 2;
+constexpr int kStDeferOverflow = 4;
+constexpr int kStExactRange = 8;
+constexpr int kStDegenLimit = 16;
+// internal: the exact integer copy of this query is unusable
+constexpr int kStNoExactInts = 1 << 8;
+
+// Per-query state written by the preparation kernel and the subset kernels.
+struct QueryState {
+    int32_t nnz;        // n' = number of observations different from the query
+    int32_t n0;         // observations equal to the query
+    int32_t status;     // kSt* bits
+    int32_t min_term;   // running minimum of delta_I + b_I (atomicMin)
+};
+
+// Per-query description (one entry per query of every problem in a call).
+struct QueryDesc {
+    const double* X;    // n x p, device
+    const double* z;    // p, device
+    int32_t* count;     // output slot, device
+    int32_t n, p;
+    int32_t M;          // sort width: power of two >= n - (p-2), >= 64
+    int32_t idx_bits;   // bits of the point index inside a 32-bit key
+    uint64_t x_off;     // offset (elements) of this query's arrays in the pools
+    uint64_t item_begin;// first global work item of this query
+    uint32_t items;     // work items of this query
+    int32_t cls;        // (p, K) class index for the batched dispatcher
+};
+
+// Deferred (uncertain) subset.
+struct Deferred {
+    uint32_t query;
+    uint32_t pad;
+    uint64_t rank;
+};
+
+// Device counters accumulated per call.
+struct Counters {
+    unsigned long long swept;
+    unsigned long long fp64_rechecks;
+    unsigned long long deferred;
+    unsigned long long exact_preds;
+    unsigned long long degenerate;
+    unsigned long long invalid;
+    unsigned long long work_next;     // work-item counter of the subset kernels
+    unsigned long long defer_next;    // deferred-queue write position
+    unsigned long long exact_next;    // deferred-queue read position
+    unsigned long long prep_next;     // query counter of the preparation kernel
+    unsigned long long fin_next;      // query counter of the finalisation
+    unsigned long long pad[5];
+};
+
+// Pools of per-query arrays (offsets in QueryDesc::x_off, in points*p units
+// for the AoS arrays and points for nrm).
+struct Pools {
+    double* x64;        // centred points, float64, AoS [M][p]
+    float* x32;         // centred points, float32, AoS [M][p]
+    float* nrm;         // upper bound of ||x||_2 per point [M]
+    uint64_t* xi;       // exact integers (x - z) * 2^-E, two's complement
+                        // 128-bit (lo, hi) pairs, AoS [M][p][2]
+    const uint64_t* binom;  // binomial table [kBinomN][kBinomK]
+    QueryState* qs;
+    const QueryDesc* qd;
+    Deferred* deferred;
+    Counters* ctr;
+    uint64_t defer_cap;
+    uint64_t total_items;
+    int32_t num_queries;
+    int32_t chunk;      // subsets per work item (multiple of 64)
+    float filter_scale;
+    int32_t force_exact;
+    uint8_t* wscratch;       // per-block scratch in device memory
+    uint64_t wscratch_bytes; // bytes per block
+};
+
+// Bytes of per-block scratch the subset kernels need for a sort width M.
+inline constexpr uint64_t wave_scratch_bytes(int M) {
+    // float64 basis slots: 64 x (2*kMaxP + 2) doubles; staging: M x (4+4+1+8+4)
+    return (uint64_t)64 * (2 * kMaxP + 2) * 8 + (uint64_t)M * 21 + 256;
+}
+
+}  // namespace td

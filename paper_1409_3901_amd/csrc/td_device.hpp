@@ -1,0 +1,431 @@
+// Device building blocks of the subset kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "td_common.hpp"
+
+namespace td {
+
+constexpr double kU64 = 1.1102230246251565e-16;  // 2^-53
+constexpr float kU32 = 5.9604645e-08f;            // 2^-24
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+// Values known to be equal on every lane, moved to scalar registers.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ float unif(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// ------------------------------------------------------------ wave helpers
+template <typename T>
+__device__ __forceinline__ T shfl_xor_t(T v, int mask) {
+    return __shfl_xor(v, mask, 64);
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// exclusive prefix sum over the 64 lanes
+__device__ __forceinline__ int wave_excl_sum(int v) {
+    const int lane = lane_id();
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x - v;
+}
+
+// exclusive prefix max over the 64 lanes (identity `id` for lane 0)
+__device__ __forceinline__ int wave_excl_max(int v, int id) {
+    const int lane = lane_id();
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x = max(x, y);
+    }
+    int prev = __shfl_up(x, 1, 64);
+    return lane == 0 ? id : prev;
+}
+
+// ------------------------------------------------------------ bitonic sort
+// Ascending sort of M = 64*K keys held blocked: element e = lane*K + i lives
+// in register i of lane `lane`.  The flip form of the bitonic network is used
+// (first stage of every merge compares e with e ^ (size-1)), so every
+// compare-exchange puts the minimum at the lower position.
+template <typename T>
+__device__ __forceinline__ void ce(T& a, T& b) {
+    T lo = a < b ? a : b;
+    T hi = a < b ? b : a;
+    a = lo;
+    b = hi;
+}
+
+template <int K, typename T>
+__device__ __forceinline__ void flip_stage(T (&v)[K], int size, int lane) {
+    if (size <= K) {
+#pragma unroll
+        for (int b = 0; b < K; b += size)
+#pragma unroll
+            for (int i = 0; i < size / 2; ++i) ce(v[b + i], v[b + size - 1 - i]);
+    } else {
+        const int lm = size / K - 1;
+        const bool lower = (lane & (size / (2 * K))) == 0;
+        T w[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) w[i] = shfl_xor_t(v[K - 1 - i], lm);
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            T a = v[i], b = w[i];
+            T lo = a < b ? a : b, hi = a < b ? b : a;
+            v[i] = lower ? lo : hi;
+        }
+    }
+}
+
+template <int K, typename T>
+__device__ __forceinline__ void half_stage(T (&v)[K], int d, int lane) {
+    if (d < K) {
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if ((i & d) == 0) ce(v[i], v[i | d]);
+    } else {
+        const int lm = d / K;
+        const bool lower = (lane & lm) == 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            T a = v[i], b = shfl_xor_t(v[i], lm);
+            T lo = a < b ? a : b, hi = a < b ? b : a;
+            v[i] = lower ? lo : hi;
+        }
+    }
+}
+
+template <int K, typename T>
+__device__ __forceinline__ void wave_sort(T (&v)[K]) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int size = 2; size <= 64 * K; size <<= 1) {
+        flip_stage<K>(v, size, lane);
+#pragma unroll
+        for (int d = size >> 2; d >= 1; d >>= 1) half_stage<K>(v, d, lane);
+    }
+}
+
+// --------------------------------------------------------- binomial / rank
+__device__ __forceinline__ uint64_t binom_lookup(const uint64_t* tab, int n, int k) {
+    if (k < 0 || n < k) return 0;
+    return tab[n * kBinomK + k];
+}
+
+// Colexicographic unranking of k-subsets: rank = sum_i C(c_i, i+1) with
+// c_0 < c_1 < ... < c_{k-1}.  The map does not depend on the ground-set size,
+// so ranks below C(n', k) give subsets of {0..n'-1}.
+template <int KS>
+__device__ __forceinline__ void unrank_colex(const uint64_t* tab, uint64_t r, int nmax, int (&c)[KS > 0 ? KS : 1]) {
+    int hi = nmax;  // exclusive upper bound for the current element
+#pragma unroll
+    for (int i = KS; i >= 1; --i) {
+        // largest x in [i-1, hi-1] with C(x, i) <= r
+        int lo = i - 1, h = hi - 1;
+        while (lo < h) {
+            int mid = (lo + h + 1) >> 1;
+            if (binom_lookup(tab, mid, i) <= r) lo = mid; else h = mid - 1;
+        }
+        c[i - 1] = lo;
+        r -= binom_lookup(tab, lo, i);
+        hi = lo;
+    }
+}
+
+// -------------------------------------------- minors of the p x (p-2) block
+// Combination tables (rows of a p-row matrix) for the Laplace recursion that
+// computes every c x c minor of the first c columns from the (c-1) x (c-1)
+// minors.  Level c lists the c-subsets of rows in increasing mask order.
+template <int P>
+struct ComboTab {
+    int cnt[P + 1];
+    uint8_t mask[P + 1][70];
+    uint8_t rows[P + 1][70][8];
+    uint8_t child[P + 1][70][8];
+};
+
+constexpr int pc8(int m) {
+    int c = 0;
+    for (int b = 0; b < 8; ++b) c += (m >> b) & 1;
+    return c;
+}
+
+template <int P>
+constexpr ComboTab<P> make_combo_tab() {
+    ComboTab<P> T{};
+    for (int c = 0; c <= P; ++c) {
+        int t = 0;
+        for (int m = 0; m < (1 << P); ++m) {
+            if (pc8(m) != c) continue;
+            T.mask[c][t] = (uint8_t)m;
+            int r = 0;
+            for (int b = 0; b < P; ++b)
+                if ((m >> b) & 1) T.rows[c][t][r++] = (uint8_t)b;
+            ++t;
+        }
+        T.cnt[c] = t;
+    }
+    for (int c = 1; c <= P; ++c)
+        for (int t = 0; t < T.cnt[c]; ++t)
+            for (int pos = 0; pos < c; ++pos) {
+                int m2 = T.mask[c][t] ^ (1 << T.rows[c][t][pos]);
+                for (int u = 0; u < T.cnt[c - 1]; ++u)
+                    if (T.mask[c - 1][u] == m2) T.child[c][t][pos] = (uint8_t)u;
+            }
+    return T;
+}
+
+// Index of the level-(P-2) combination that leaves out rows a and b.
+template <int P>
+constexpr int pair_combo(int a, int b) {
+    constexpr ComboTab<P> T = make_combo_tab<P>();
+    int m = ((1 << P) - 1) ^ (1 << a) ^ (1 << b);
+    for (int u = 0; u < T.cnt[P - 2]; ++u)
+        if (T.mask[P - 2][u] == m) return u;
+    return -1;
+}
+
+template <int P>
+struct MinorSet {
+    // value of every (p-2)-minor, indexed by the combination of P-2 rows
+    double v[70];
+};
+
+// All (p-2) x (p-2) minors of A (p rows, p-2 columns; A[r][c]) by the Laplace
+// recursion along the last column.
+template <int P>
+__device__ __forceinline__ void all_minors(const double (&A)[P][P > 2 ? P - 2 : 1], MinorSet<P>& out) {
+    constexpr int KC = P - 2;
+    constexpr ComboTab<P> T = make_combo_tab<P>();
+    double pv[70];
+    if (KC == 0) {
+        out.v[0] = 1.0;
+        return;
+    }
+#pragma unroll
+    for (int t = 0; t < T.cnt[1]; ++t) pv[t] = A[T.rows[1][t][0]][0];
+#pragma unroll
+    for (int c = 2; c <= KC; ++c) {
+        double cv[70];
+#pragma unroll
+        for (int t = 0; t < T.cnt[c]; ++t) {
+            double v = 0.0;
+#pragma unroll
+            for (int pos = 0; pos < c; ++pos) {
+                const double x = A[T.rows[c][t][pos]][c - 1];
+                v = fma(((pos + c - 1) & 1) ? -x : x, pv[T.child[c][t][pos]], v);
+            }
+            cv[t] = v;
+        }
+#pragma unroll
+        for (int t = 0; t < T.cnt[c]; ++t) pv[t] = cv[t];
+    }
+#pragma unroll
+    for (int t = 0; t < T.cnt[KC]; ++t) out.v[t] = pv[t];
+}
+
+// Rounding bound of every minor: the sum over the expansion of the absolute
+// monomials is at most the product of the column 1-norms, and every monomial
+// passes through at most k input roundings plus c roundings at level c.
+template <int P>
+constexpr double minor_gamma() {
+    constexpr int k = P - 2;
+    constexpr int N = k + k * (k + 1) / 2 + 3;
+    return (double)N * kU64 * 1.0001;
+}
+
+// ------------------------------------------------------ complement basis
+// Orthonormal basis (e1, e2) of the orthogonal complement of span(x_I), the
+// first step of Algorithm 1.  Construction: for the row pair (j,k) with the
+// largest certified minor omega = det[x_I | e_j | e_k], the vectors
+//     g1_i = det[x_I | e_i | e_j],   g2_i = det[x_I | e_i | e_k]
+// are exactly orthogonal to span(x_I) and span its complement; e1, e2 are
+// their Gram-Schmidt orthonormalisation.  The exact linear maps
+//     L1 = s1 g1,   L2 = s2 (g2 - c s1 g1)
+// (s1, s2, c the float64 coefficients actually used) form the exact frame the
+// float computations approximate: L = T phi with phi(x) = (g1.x, g2.x) and
+// T lower triangular with positive diagonal, so orientations and the fold
+// half-plane {L1 x > 0} U {L1 x = 0, L2 x > 0} are those of phi.
+// `eta` bounds ||e_k - L_k||_1 for both k (input rounding included).
+template <int P>
+struct Basis {
+    double e1[P], e2[P];
+    double s1, s2, c;
+    double eta;
+    int j, k;
+    int certified;   // 1: some minor is certified nonzero (the subset is valid)
+    int anynz;       // 1: the largest float64 minor is nonzero
+};
+
+// Gram-Schmidt of the Pluecker rows g1, g2 (absolute errors E1, E2 against
+// the exact rows) into e1, e2, with the frame coefficients and eta.
+template <int P>
+__device__ __forceinline__ void finish_basis(const double (&g1)[P], const double (&g2)[P], const double (&E1)[P],
+                                             const double (&E2)[P], Basis<P>& B) {
+    double n1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) n1 = fma(g1[i], g1[i], n1);
+    const double s1 = (n1 > 0.0) ? 1.0 / sqrt(n1) : 0.0;
+    double cc = 0.0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        B.e1[i] = g1[i] * s1;
+        cc = fma(B.e1[i], g2[i], cc);
+    }
+    double n2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        B.e2[i] = fma(-cc, B.e1[i], g2[i]);
+        n2 = fma(B.e2[i], B.e2[i], n2);
+    }
+    const double s2 = (n2 > 0.0) ? 1.0 / sqrt(n2) : 0.0;
+    // eta >= ||e_k - L_k||_1: per component
+    //   e1: s1*E1 + u|e1|,   e2: u|e2| + s2*(1.01u|v| + E2 + |c| eps1)
+    double eta1 = 0.0, eta2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const double vi = B.e2[i];
+        B.e2[i] = vi * s2;
+        const double ep1 = s1 * E1[i] + kU64 * fabs(B.e1[i]);
+        eta1 += ep1;
+        eta2 += kU64 * fabs(B.e2[i]) + s2 * (1.01 * kU64 * fabs(vi) + E2[i] + fabs(cc) * ep1);
+    }
+    B.s1 = s1;
+    B.s2 = s2;
+    B.c = cc;
+    B.eta = fmax(eta1, eta2) * 1.001;
+}
+
+template <int P>
+__device__ __forceinline__ void build_basis(const double (&A)[P][P > 2 ? P - 2 : 1], Basis<P>& B) {
+    MinorSet<P> ms;
+    all_minors<P>(A, ms);
+    // bound on the rounding error of every minor
+    double colprod = 1.0;
+#pragma unroll
+    for (int c = 0; c < P - 2; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < P; ++r) s += fabs(A[r][c]);
+        colprod *= s;
+    }
+    const double emin = minor_gamma<P>() * colprod * 1.0001;
+    // pivot pair: largest |minor|; certified when it exceeds the bound
+    double best = -1.0;
+    int bj = 0, bk = 1;
+#pragma unroll
+    for (int a = 0; a < P; ++a)
+#pragma unroll
+        for (int b = a + 1; b < P; ++b) {
+            const double v = fabs(ms.v[pair_combo<P>(a, b)]);
+            if (v > best) { best = v; bj = a; bk = b; }
+        }
+    B.certified = best > emin;
+    B.anynz = best > 0.0;
+    B.j = bj;
+    B.k = bk;
+    double g1[P], g2[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        // det[A | e_i | e_j] = (-1)^(j + i' + 1) M_{ij},  i' = i - [i > j]
+        double v1 = 0.0, v2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+#pragma unroll
+            for (int b = a + 1; b < P; ++b) {
+                const double mv = ms.v[pair_combo<P>(a, b)];
+                if ((a == i && b == bj) || (b == i && a == bj)) v1 = mv;
+                if ((a == i && b == bk) || (b == i && a == bk)) v2 = mv;
+            }
+        const int i1 = i - (i > bj ? 1 : 0);
+        const int i2 = i - (i > bk ? 1 : 0);
+        g1[i] = (i == bj) ? 0.0 : ((((bj + i1 + 1) & 1) ? -v1 : v1));
+        g2[i] = (i == bk) ? 0.0 : ((((bk + i2 + 1) & 1) ? -v2 : v2));
+    }
+    double E1[P], E2[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        E1[i] = (i == bj) ? 0.0 : emin;
+        E2[i] = (i == bk) ? 0.0 : emin;
+    }
+    finish_basis<P>(g1, g2, E1, E2, B);
+}
+
+// ------------------------------------------------------- exact 128-bit input
+__device__ __forceinline__ int low_exp(double v) {
+    // exponent of the lowest set bit of a finite nonzero double
+    uint64_t b = (uint64_t)__double_as_longlong(v);
+    int ex = (int)((b >> 52) & 0x7ff);
+    uint64_t man = b & 0xfffffffffffffull;
+    if (ex == 0) {  // subnormal
+        return -1074 + __builtin_ctzll(man);
+    }
+    man |= (1ull << 52);
+    return ex - 1075 + __builtin_ctzll(man);
+}
+
+__device__ __forceinline__ int high_exp(double v) {
+    // exponent of the highest set bit of a finite nonzero double
+    uint64_t b = (uint64_t)__double_as_longlong(v);
+    int ex = (int)((b >> 52) & 0x7ff);
+    uint64_t man = b & 0xfffffffffffffull;
+    if (ex == 0) return -1074 + 63 - __builtin_clzll(man);
+    return ex - 1023;
+}
+
+// v * 2^-E as a two's-complement 128-bit integer (lo, hi); requires v to be a
+// multiple of 2^E and |v| * 2^-E < 2^126.
+__device__ __forceinline__ void to_i128(double v, int E, uint64_t& lo, uint64_t& hi) {
+    lo = 0;
+    hi = 0;
+    if (v == 0.0) return;
+    uint64_t b = (uint64_t)__double_as_longlong(v);
+    int ex = (int)((b >> 52) & 0x7ff);
+    uint64_t man = b & 0xfffffffffffffull;
+    int e2;
+    if (ex == 0) { e2 = -1074; } else { man |= (1ull << 52); e2 = ex - 1075; }
+    int sh = e2 - E;   // >= 0 by the choice of E... may be negative for low bits that are zero
+    while (sh < 0) { man >>= 1; ++sh; }
+    if (sh >= 128) { lo = 0; hi = 0; }
+    else if (sh >= 64) { hi = man << (sh - 64); lo = 0; }
+    else if (sh == 0) { lo = man; hi = 0; }
+    else { lo = man << sh; hi = man >> (64 - sh); }
+    if (b >> 63) {  // negate
+        lo = ~lo;
+        hi = ~hi;
+        lo += 1;
+        if (lo == 0) hi += 1;
+    }
+}
+
+}  // namespace td

@@ -1,0 +1,213 @@
+// Preparation, initialisation and finalisation kernels.
+#include <hip/hip_runtime.h>
+
+#include "td_common.hpp"
+#include "td_device.hpp"
+
+namespace td {
+
+// Clears the per-call counters (a kernel, not a memset, so the whole call can
+// be captured in a graph and replayed).
+__global__ void init_kernel(Counters* ctr) {
+    unsigned long long* c = reinterpret_cast<unsigned long long*>(ctr);
+    const int n = (int)(sizeof(Counters) / sizeof(unsigned long long));
+    for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0ull;
+}
+
+// One block of 256 threads per query (persistent over queries).  Shift to the
+// query (Section 2: x_i = X_i - z), drop the observations equal to it (they
+// lie on every hyperplane through z and add n0 to every count), and store
+// the nonzero points compacted in input order:
+//   x64 : float64 centred values (one rounding),
+//   x32 : float32 copies,
+//   nrm : float32 upper bound of ||x||_2 of the float64 values,
+//   xi  : exact integers (X - z) * 2^-E, E the lowest bit exponent over the
+//         query's inputs (two's complement, 128 bits).
+// p = 1 needs no subsets: the count is n0 + min(#{x > 0}, #{x < 0}).
+__global__ __launch_bounds__(256) void prep_kernel(Pools pl) {
+    __shared__ int s_flag[kMaxN];
+    __shared__ int s_pos[kMaxN];
+    __shared__ int s_red[8];
+    __shared__ int s_q;
+    __shared__ double s_z[kMaxP];
+    const int tid = threadIdx.x;
+    while (true) {
+        if (tid == 0) s_q = (int)atomicAdd(&pl.ctr->prep_next, 1ull);
+        __syncthreads();
+        const int q = s_q;
+        __syncthreads();
+        if (q >= pl.num_queries) break;
+        const QueryDesc d = pl.qd[q];
+        const int n = d.n, p = d.p, M = d.M;
+        if (tid < p) s_z[tid] = d.z[tid];
+        __syncthreads();
+        int bad = 0;
+        if (tid < p && !isfinite(s_z[tid])) bad = 1;
+        // nonzero flags
+        for (int i = tid; i < n; i += blockDim.x) {
+            int nz = 0;
+            for (int c = 0; c < p; ++c) {
+                const double v = d.X[(size_t)i * p + c];
+                if (!isfinite(v)) bad = 1;
+                if (v != s_z[c]) nz = 1;
+            }
+            s_flag[i] = nz;
+        }
+        // lowest / highest bit exponents over the inputs (for the exact copy)
+        int emin = 1 << 20, emax = -(1 << 20);
+        for (int i = tid; i < n * p; i += blockDim.x) {
+            const double v = d.X[i];
+            if (v != 0.0 && isfinite(v)) {
+                emin = min(emin, low_exp(v));
+                emax = max(emax, high_exp(v));
+            }
+        }
+        if (tid < p && s_z[tid] != 0.0 && isfinite(s_z[tid])) {
+            emin = min(emin, low_exp(s_z[tid]));
+            emax = max(emax, high_exp(s_z[tid]));
+        }
+        __syncthreads();
+        // block reductions: bad (or), emin, emax
+        {
+            int v = bad;
+            for (int o = 32; o >= 1; o >>= 1) v |= __shfl_xor(v, o, 64);
+            int a = wave_min(emin), b = wave_max(emax);
+            if ((tid & 63) == 0) { s_red[tid >> 6] = v; s_red[4 + (tid >> 6)] = a; }
+            __syncthreads();
+            if (tid == 0) {
+                int o = 0, mn = 1 << 20;
+                for (int w = 0; w < 4; ++w) { o |= s_red[w]; mn = min(mn, s_red[4 + w]); }
+                s_red[0] = o;
+                s_red[1] = mn;
+            }
+            __syncthreads();
+            bad = s_red[0];
+            emin = s_red[1];
+            __syncthreads();
+            if ((tid & 63) == 0) s_red[4 + (tid >> 6)] = b;
+            __syncthreads();
+            if (tid == 0) {
+                int mx = -(1 << 20);
+                for (int w = 0; w < 4; ++w) mx = max(mx, s_red[4 + w]);
+                s_red[2] = mx;
+            }
+            __syncthreads();
+            emax = s_red[2];
+        }
+        // order-preserving compaction: scan of the flags
+        if (tid == 0) {
+            int acc = 0;
+            for (int i = 0; i < n; ++i) { s_pos[i] = acc; acc += s_flag[i]; }
+            s_red[3] = acc;
+        }
+        __syncthreads();
+        const int nnz = s_red[3];
+        const uint64_t off = d.x_off;
+        double* x64 = pl.x64 + off * p;
+        float* x32 = pl.x32 + off * p;
+        float* nrm = pl.nrm + off;
+        uint64_t* xi = pl.xi + off * p * 2;
+        const bool ints_ok = (emax - emin + 2) <= 125 && emin < (1 << 19);
+        for (int i = tid; i < M; i += blockDim.x) {
+            // padding rows beyond nnz are zero
+            if (i >= nnz) {
+                for (int c = 0; c < p; ++c) {
+                    x64[(size_t)i * p + c] = 0.0;
+                    x32[(size_t)i * p + c] = 0.0f;
+                    xi[((size_t)i * p + c) * 2] = 0;
+                    xi[((size_t)i * p + c) * 2 + 1] = 0;
+                }
+                nrm[i] = 0.0f;
+            }
+        }
+        for (int i = tid; i < n; i += blockDim.x) {
+            if (!s_flag[i]) continue;
+            const int j = s_pos[i];
+            double ss = 0.0;
+            for (int c = 0; c < p; ++c) {
+                const double xv = d.X[(size_t)i * p + c];
+                const double v = xv - s_z[c];
+                x64[(size_t)j * p + c] = v;
+                x32[(size_t)j * p + c] = (float)v;
+                ss = fma(v, v, ss);
+                uint64_t lo = 0, hi = 0;
+                if (ints_ok) {
+                    uint64_t alo, ahi, blo, bhi;
+                    to_i128(xv, emin, alo, ahi);
+                    to_i128(s_z[c], emin, blo, bhi);
+                    lo = alo - blo;
+                    hi = ahi - bhi - (alo < blo ? 1ull : 0ull);
+                }
+                xi[((size_t)j * p + c) * 2] = lo;
+                xi[((size_t)j * p + c) * 2 + 1] = hi;
+            }
+            // rounding-safe upper bound: relative slack far above the few ulps
+            // of the sum, the square root and the conversion to float32
+            nrm[j] = (float)(sqrt(ss) * (1.0 + 1e-6));
+        }
+        // p = 1: closed form
+        int pos1 = 0, neg1 = 0;
+        if (p == 1) {
+            for (int i = tid; i < n; i += blockDim.x) {
+                const double v = d.X[i] - s_z[0];
+                pos1 += v > 0.0;
+                neg1 += v < 0.0;
+            }
+            pos1 = wave_sum(pos1);
+            neg1 = wave_sum(neg1);
+            __syncthreads();
+            if ((tid & 63) == 0) { s_red[tid >> 6] = pos1; s_red[4 + (tid >> 6)] = neg1; }
+            __syncthreads();
+            if (tid == 0) {
+                pos1 = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+                neg1 = s_red[4] + s_red[5] + s_red[6] + s_red[7];
+            }
+        }
+        if (tid == 0) {
+            QueryState st;
+            st.nnz = nnz;
+            st.n0 = n - nnz;
+            st.status = (bad ? kStNonfinite : 0) | (ints_ok ? 0 : kStNoExactInts);
+            st.min_term = 0x7fffffff;
+            if (p == 1) st.min_term = min(pos1, neg1);
+            if (nnz == 0) st.min_term = 0;
+            pl.qs[q] = st;
+        }
+        __syncthreads();
+    }
+}
+
+// counts[q] = n0 + min over subsets, or -1 with a status bit.
+__global__ void finalize_kernel(Pools pl) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < pl.num_queries; q += gridDim.x * blockDim.x) {
+        QueryState st = pl.qs[q];
+        int bad = st.status & (kStNonfinite | kStDeferOverflow | kStExactRange | kStDegenLimit);
+        int out;
+        if (bad) {
+            out = -1;
+        } else if (st.min_term == 0x7fffffff) {
+            out = -1;
+            st.status |= kStNoValid;
+            pl.qs[q].status = st.status;
+        } else {
+            out = st.n0 + st.min_term;
+        }
+        *pl.qd[q].count = out;
+    }
+}
+
+}  // namespace td
+
+extern "C" hipError_t td_launch_prep(const td::Pools* pl, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(td::init_kernel, dim3(1), dim3(64), 0, s, pl->ctr);
+    hipLaunchKernelGGL(td::prep_kernel, dim3(blocks), dim3(256), 0, s, *pl);
+    return hipGetLastError();
+}
+
+extern "C" hipError_t td_launch_finalize(const td::Pools* pl, hipStream_t s) {
+    int blocks = (pl->num_queries + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(td::finalize_kernel, dim3(blocks), dim3(256), 0, s, *pl);
+    return hipGetLastError();
+}

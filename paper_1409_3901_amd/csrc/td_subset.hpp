@@ -1,0 +1,579 @@
+// The subset kernel: Algorithm 1's loop over (p-2)-subsets with Algorithm 2
+// (projection, angular sort, circular sweep) as the per-subset step.
+//
+// Layout: one wave64 per workgroup.  A work item is a range of `chunk`
+// consecutive colex ranks of one query; waves pull items from a device
+// counter until none is left (persistent grid).  The points of the current
+// query stay in registers: lane L holds points L*K .. L*K+K-1 (blocked), so
+// the sort starts with element e = point e.  Bases are built 64 at a time,
+// one subset per lane, and staged in LDS; the wave then sweeps the 64 subsets
+// one after the other, every lane taking part in each sweep.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "td_common.hpp"
+#include "td_device.hpp"
+
+namespace td {
+
+constexpr int kDefer = -2;
+constexpr int kSkip = -3;
+constexpr int kBig = 0x7fffffff;
+
+template <int P>
+struct SlotPlain {
+    double e1[P], e2[P];
+    int16_t mem[P > 2 ? P - 2 : 1];
+    int32_t state;   // 0 ok, 1 skip
+};
+
+template <int P>
+struct SlotFilt {        // LDS: what every sweep reads
+    float f1[P], f2[P];
+    float beta32;    // float32 projection error <= beta32 * ||x||_2
+    int32_t state;   // 0 ok, 1 skip (out of range / invalid), 3 defer
+    int16_t mem[P > 2 ? P - 2 : 1];
+};
+
+template <int P>
+struct SlotF64 {         // device scratch: read only by float64 re-checks
+    double e1[P], e2[P];
+    double beta64;   // float64 projection error <= beta64 * ||x||_2
+    double pad;
+};
+
+// Per-block staging for the rare re-ordering of uncertain runs.
+struct Staging {
+    uint32_t* pkey;
+    int* pS;
+    uint8_t* pflag;
+    double* rt;
+    float* rr;
+};
+
+// f(S) = min(S, m - S): the smaller side of the line through the origin.
+__device__ __forceinline__ int fside(int s, int m) { return min(s, m - s); }
+
+// Which query a global work item belongs to (binary search on item_begin).
+__device__ __forceinline__ int item_query(const QueryDesc* qd, int nq, uint64_t item) {
+    int lo = 0, hi = nq - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (qd[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------- plain
+template <int P, int K>
+__device__ int sweep_plain(const double (&xr)[K][P], const SlotPlain<P>& S, int nnz) {
+    constexpr int KS = P - 2;
+    const int lane = lane_id();
+    double e1[P], e2[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        e1[c] = S.e1[c];
+        e2[c] = S.e2[c];
+    }
+    int mem[KS > 0 ? KS : 1];
+#pragma unroll
+    for (int c = 0; c < KS; ++c) mem[c] = uni(S.mem[c]);
+    uint64_t key[K];
+    int zc = 0, nplus = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int idx = lane * K + i;
+        bool valid = idx < nnz;
+#pragma unroll
+        for (int c = 0; c < KS; ++c) valid = valid && (idx != mem[c]);
+        double y1 = 0.0, y2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+            y1 = fma(e1[c], xr[i][c], y1);
+            y2 = fma(e2[c], xr[i][c], y2);
+        }
+        uint64_t kk = ~0ull;
+        if (valid) {
+            if (y1 == 0.0 && y2 == 0.0) {
+                ++zc;   // projects to the origin (Algorithm 2, Step 1(a))
+            } else {
+                const bool pos = (y1 > 0.0) || (y1 == 0.0 && y2 > 0.0);
+                const double h1 = pos ? y1 : -y1;
+                const double h2 = pos ? y2 : -y2;
+                const double t = h2 / (h1 + fabs(h2)) + 1.0;   // pseudo-angle in (0, 2]
+                kk = ((uint64_t)__double_as_longlong(t) & ~1ull) | (pos ? 0ull : 1ull);
+                nplus += pos ? 1 : 0;
+            }
+        }
+        key[i] = kk;
+    }
+    wave_sort<K>(key);
+    const int ztot = wave_sum(zc);
+    const int m = nnz - KS - ztot;
+    const int S0 = wave_sum(nplus);
+    int dl[K];
+    int loc = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        dl[i] = (key[i] == ~0ull) ? 0 : ((key[i] & 1ull) ? 1 : -1);
+        loc += dl[i];
+    }
+    int s = S0 + wave_excl_sum(loc);
+    const uint64_t nxt = __shfl_down(key[0], 1, 64);
+    int best = (lane == 0) ? fside(S0, m) : kBig;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        s += dl[i];
+        const uint64_t nk = (i + 1 < K) ? key[i + 1] : ((lane == 63) ? ~0ull : nxt);
+        const bool real = key[i] != ~0ull;
+        const bool run_end = real && (nk == ~0ull || ((key[i] >> 1) != (nk >> 1)));
+        if (run_end) best = min(best, fside(s, m));
+    }
+    return wave_min(best) + ztot;
+}
+
+// ---------------------------------------------------------------- filtered
+// Side table entry of a point (LDS, indexed by point): interval half-width in
+// key quanta (15 bits) and the sign bit set when the point was folded
+// (delta = +1).
+constexpr uint32_t kSideNeg = 0x8000u;
+constexpr int kRqMax = 4096;    // larger radius: re-check in float64
+constexpr int kClusterMax = 64; // larger uncertain run: defer to the exact tier
+
+struct FiltCtx {
+    const double* x64;  // this query's float64 points (AoS)
+    const float* nrm;
+    float fscale;       // filter scale
+    int idx_bits;
+};
+
+template <int P>
+__device__ __forceinline__ void fp64_point(const double* x64, const double (&e1)[P], const double (&e2)[P],
+                                           int idx, double& y1, double& y2) {
+    y1 = 0.0;
+    y2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        const double v = x64[(size_t)idx * P + c];
+        y1 = fma(e1[c], v, y1);
+        y2 = fma(e2[c], v, y2);
+    }
+}
+
+// Float64 key and radius of a point (in the pseudo-angle t' = t + 1 in [0,2]);
+// returns false if the fold or the magnitude is not certified.
+__device__ __forceinline__ bool key64(double y1, double y2, double eps, bool& pos, double& t, double& r) {
+    if (!(fabs(y1) > eps)) return false;
+    pos = y1 > 0.0;
+    const double h1 = fabs(y1);
+    const double h2 = pos ? y2 : -y2;
+    const double s = h1 + fabs(h2);
+    if (!(s > 4.0 * eps)) return false;
+    t = h2 / s + 1.0;
+    r = eps / (s - 2.0 * eps) * 1.001 + 4.0 * kU64;
+    return true;
+}
+
+template <int P, int K>
+__device__ int sweep_filt(const float (&xr)[K][P], const float (&nr)[K], const SlotFilt<P>& S,
+                          const SlotF64<P>& S64, int nnz, const FiltCtx& fc, uint16_t* side, const Staging& sg,
+                          unsigned long long& rechecks) {
+    uint32_t* pkey = sg.pkey;
+    int* pS = sg.pS;
+    uint8_t* pflag = sg.pflag;
+    double* rt = sg.rt;
+    float* rr = sg.rr;
+    constexpr int KS = P - 2;
+    const int lane = lane_id();
+    const int ib = fc.idx_bits;
+    const uint32_t imask = (1u << ib) - 1u;
+    const int B = 32 - ib;
+    const double qscale = (double)(1u << (B - 1));
+    const float qscalef = (float)qscale;
+    const uint32_t qmax = (1u << B) - 2u;   // keeps every real key below the pad value
+    // float32 basis and error coefficient in registers; the float64 basis is
+    // read from LDS only by the rare re-checks
+    float f1[P], f2[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        f1[c] = unif(S.f1[c]);
+        f2[c] = unif(S.f2[c]);
+    }
+    int mem[KS > 0 ? KS : 1];
+#pragma unroll
+    for (int c = 0; c < KS; ++c) mem[c] = uni(S.mem[c]);
+    const float beta = unif(S.beta32 * fc.fscale);
+    uint32_t key[K];
+    int nplus = 0;
+    uint32_t weak = 0;   // points whose float32 key is not certified
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int idx = lane * K + i;
+        bool valid = idx < nnz;
+#pragma unroll
+        for (int c = 0; c < KS; ++c) valid = valid && (idx != mem[c]);
+        float y1 = 0.0f, y2 = 0.0f;
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+            y1 = fmaf(f1[c], xr[i][c], y1);
+            y2 = fmaf(f2[c], xr[i][c], y2);
+        }
+        // Fold into {h1 > 0} U {h1 = 0, h2 > 0} by the sign of the first
+        // coordinate; pseudo-angle t' = h2 / (h1 + |h2|) + 1 in (0, 2], which
+        // is strictly increasing with the angle on that half-plane.  With the
+        // float32 error eps of each coordinate the key error is at most
+        // eps / (s - 2 eps) plus the rounding of t' (Algorithm 2, Step 1(b)).
+        const float eps = beta * nr[i];
+        const bool pos = y1 > 0.0f;
+        const float h1 = fabsf(y1);
+        const float h2 = pos ? y2 : -y2;
+        const float s = h1 + fabsf(h2);
+        // __fdividef is within 2 ulp: covered by the 8 u32 term and the 1.001
+        const float t = __fdividef(h2, s) + 1.0f;
+        const float r = __fdividef(eps, s - 2.0f * eps) * 1.001f + 8.0f * kU32;
+        const float rqf = r * qscalef;
+        const bool ok = (h1 > eps) && (s > 4.0f * eps) && (rqf < (float)kRqMax);
+        uint32_t kk = 0xffffffffu;
+        if (valid) {
+            if (ok) {
+                const uint32_t q = min((uint32_t)(t * qscalef), qmax);
+                const uint32_t rq = (uint32_t)rqf + 4u;
+                kk = (q << ib) | (uint32_t)idx;
+                side[idx] = (uint16_t)(rq | (pos ? 0u : kSideNeg));
+                nplus += pos ? 1 : 0;
+            } else {
+                weak |= 1u << i;
+            }
+        }
+        key[i] = kk;
+    }
+    int defer = 0;
+    if (__any(weak != 0)) {
+        // float32 cannot settle the fold or the angle: float64 re-check
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            if (!((weak >> i) & 1u)) continue;
+            const int idx = lane * K + i;
+            ++rechecks;
+            double d1, d2, t, r;
+            bool pos;
+            fp64_point<P>(fc.x64, S64.e1, S64.e2, idx, d1, d2);
+            const double eps64 = S64.beta64 * (double)nr[i];
+            if (key64(d1, d2, eps64, pos, t, r) && r * qscale < (double)kRqMax) {
+                const uint32_t q = min((uint32_t)(t * qscale), qmax);
+                const uint32_t rq = (uint32_t)(r * qscale) + 4u;
+                key[i] = (q << ib) | (uint32_t)idx;
+                side[idx] = (uint16_t)(rq | (pos ? 0u : kSideNeg));
+                nplus += pos ? 1 : 0;
+            } else {
+                defer = 1;
+            }
+        }
+        if (__any(defer)) return kDefer;
+    }
+    __syncthreads();   // side table visible to every lane
+    wave_sort<K>(key);
+    const int m = nnz - KS;
+    const int S0 = wave_sum(nplus);
+    // Pass 1: per-lane sum of delta and max of the interval ends.
+    int loc = 0, lmax = -kBig;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        if (key[i] != 0xffffffffu) {
+            const uint32_t sd = side[key[i] & imask];
+            loc += (sd & kSideNeg) ? 1 : -1;
+            lmax = max(lmax, (int)(key[i] >> ib) + (int)(sd & 0x7fffu));
+        }
+    }
+    const int pm0 = wave_excl_max(lmax, -kBig);
+    const int s0 = S0 + wave_excl_sum(loc);
+    // Pass 2: cluster starts (interval disjoint from everything before),
+    // states after each element, and runs holding both fold signs.  The state
+    // after element e is legitimate when e ends a cluster, i.e. when the next
+    // element starts one (checked one element late).
+    int pm = pm0, s = s0;
+    uint32_t startm = 0, mixm = 0;
+    int best = (lane == 0) ? fside(S0, m) : kBig;
+    int prev_s = 0;
+    bool prev_real = false;
+    // delta of the element before this lane's first one
+    int dl_before;
+    {
+        int dl_last_lane = 0;
+        if (key[K - 1] != 0xffffffffu) dl_last_lane = (side[key[K - 1] & imask] & kSideNeg) ? 1 : -1;
+        dl_before = __shfl_up(dl_last_lane, 1, 64);
+    }
+    int dp = dl_before;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const bool real = key[i] != 0xffffffffu;
+        int dl = 0, lo = kBig, hi = -kBig;
+        if (real) {
+            const uint32_t sd = side[key[i] & imask];
+            const int rq = (int)(sd & 0x7fffu);
+            const int qv = (int)(key[i] >> ib);
+            dl = (sd & kSideNeg) ? 1 : -1;
+            lo = qv - rq;
+            hi = qv + rq;
+        }
+        const bool st = real && lo > pm;
+        pm = max(pm, hi);
+        if (st) startm |= 1u << i;
+        if (real && !st && dl != dp) mixm |= 1u << i;
+        // the previous element ends a cluster if this one starts one or is a pad
+        if (i > 0 && prev_real && (st || !real)) best = min(best, fside(prev_s, m));
+        s += dl;
+        prev_s = s;
+        prev_real = real;
+        dp = dl;
+    }
+    {
+        // last element of the lane: look at the next lane's first element
+        const int nstart = __shfl_down((int)(startm & 1u), 1, 64);
+        const int nreal = __shfl_down((int)(key[0] != 0xffffffffu), 1, 64);
+        const bool ends = (lane == 63) || nstart || !nreal;
+        if (prev_real && ends) best = min(best, fside(prev_s, m));
+    }
+    if (__any(mixm != 0)) {
+        // Runs of overlapping key intervals that hold both fold signs: their
+        // inner order matters.  Stage the sorted sequence in LDS; the lane
+        // holding the first mixed position of a run re-orders the run with
+        // float64 keys and evaluates the states between certified gaps.
+        int ss = s0;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int e = lane * K + i;
+            int dl = 0;
+            if (key[i] != 0xffffffffu) dl = (side[key[i] & imask] & kSideNeg) ? 1 : -1;
+            ss += dl;
+            pkey[e] = key[i];
+            pS[e] = ss;
+            pflag[e] = (uint8_t)(((startm >> i) & 1u) | (((mixm >> i) & 1u) << 1));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            if (!((mixm >> i) & 1u)) continue;
+            const int e = lane * K + i;
+            int a = e - 1;
+            bool first = true;
+            while (!(pflag[a] & 1)) {
+                if (pflag[a] & 2) { first = false; break; }
+                --a;
+            }
+            if (!first) continue;
+            int b = e;
+            while (b + 1 < m && !(pflag[b + 1] & 1)) ++b;
+            const int c = b - a + 1;
+            if (c > kClusterMax) { defer = 1; continue; }
+            // float64 keys of the run, insertion-sorted in place at the run's own
+            // positions of the LDS staging arrays (runs are disjoint)
+            bool ok = true;
+            for (int u = 0; u < c; ++u) {
+                const uint32_t kv = pkey[a + u];
+                const int idx = (int)(kv & imask);
+                double d1, d2, t, r;
+                bool pos;
+                fp64_point<P>(fc.x64, S64.e1, S64.e2, idx, d1, d2);
+                const double eps64 = S64.beta64 * (double)fc.nrm[idx];
+                if (!key64(d1, d2, eps64, pos, t, r)) { ok = false; break; }
+                const float rf = (float)(r * 1.0000001) + 1e-30f;   // rounded up
+                int w = u;
+                while (w > 0 && rt[a + w - 1] > t) {
+                    rt[a + w] = rt[a + w - 1];
+                    rr[a + w] = rr[a + w - 1];
+                    --w;
+                }
+                rt[a + w] = t;
+                rr[a + w] = pos ? rf : -rf;   // sign carries the fold
+            }
+            rechecks += (unsigned long long)c;
+            if (!ok) { defer = 1; continue; }
+            int sc = (a == 0) ? S0 : pS[a - 1];
+            double mhi = rt[a] + (double)fabsf(rr[a]);
+            int hasp = rr[a] < 0.0f, hasn = rr[a] > 0.0f;
+            sc += (rr[a] < 0.0f) ? 1 : -1;
+            for (int u = 1; u < c; ++u) {
+                const double tu = rt[a + u];
+                const float ru = rr[a + u];
+                if (tu - (double)fabsf(ru) > mhi) {
+                    // certified gap between u-1 and u: a legitimate state
+                    if (hasp && hasn) { ok = false; break; }
+                    best = min(best, fside(sc, m));
+                    hasp = hasn = 0;
+                }
+                hasp |= ru < 0.0f;
+                hasn |= ru > 0.0f;
+                mhi = fmax(mhi, tu + (double)fabsf(ru));
+                sc += (ru < 0.0f) ? 1 : -1;
+            }
+            if (!ok || (hasp && hasn)) defer = 1;
+        }
+        __syncthreads();
+        if (__any(defer)) return kDefer;
+    }
+    return wave_min(best);
+}
+
+// ------------------------------------------------------------------ kernel
+template <int P, int TIER>
+struct SlotOf { using type = SlotFilt<P>; };
+template <int P>
+struct SlotOf<P, kPlain> { using type = SlotPlain<P>; };
+
+template <int P>
+__device__ __forceinline__ void push_deferred(const Pools& pl, int q, uint64_t rank) {
+    const unsigned long long pos = atomicAdd(&pl.ctr->defer_next, 1ull);
+    if (pos < pl.defer_cap) {
+        Deferred d;
+        d.query = (uint32_t)q;
+        d.pad = 0;
+        d.rank = rank;
+        pl.deferred[pos] = d;
+    } else {
+        atomicOr(&pl.qs[q].status, kStDeferOverflow);
+    }
+}
+
+template <int P, int K, int TIER>
+__global__ __launch_bounds__(64) void subset_kernel(Pools pl) {
+    constexpr int KS = P - 2;
+    constexpr int M = 64 * K;
+    using Slot = typename SlotOf<P, TIER>::type;
+    __shared__ Slot slots[64];
+    __shared__ uint16_t side[TIER == kPlain ? 1 : M];
+    // per-block device scratch: float64 basis slots, then the staging arrays
+    uint8_t* wsc = pl.wscratch + (uint64_t)blockIdx.x * pl.wscratch_bytes;
+    SlotF64<P>* slots64 = reinterpret_cast<SlotF64<P>*>(wsc);
+    Staging sg;
+    {
+        uint8_t* p0 = wsc + (uint64_t)64 * (2 * kMaxP + 2) * 8;
+        sg.rt = reinterpret_cast<double*>(p0);
+        sg.pkey = reinterpret_cast<uint32_t*>(p0 + (size_t)M * 8);
+        sg.pS = reinterpret_cast<int*>(p0 + (size_t)M * 12);
+        sg.rr = reinterpret_cast<float*>(p0 + (size_t)M * 16);
+        sg.pflag = p0 + (size_t)M * 20;
+    }
+    const int lane = lane_id();
+    double xd[TIER == kPlain ? K : 1][P];
+    float xf[TIER == kPlain ? 1 : K][P];
+    float nr[TIER == kPlain ? 1 : K];
+    unsigned long long swept = 0, rechecks = 0, ndefer = 0, ninvalid = 0;
+    FiltCtx fc;
+    fc.fscale = pl.filter_scale;
+    while (true) {
+        unsigned long long item = 0;
+        if (lane == 0) item = atomicAdd(&pl.ctr->work_next, 1ull);
+        item = uni64(__shfl(item, 0, 64));
+        if (item >= pl.total_items) break;
+        const int q = uni(item_query(pl.qd, pl.num_queries, item));
+        const QueryDesc d = pl.qd[q];
+        const QueryState st = pl.qs[q];
+        if (st.status & kStNonfinite) continue;
+        const int nnz = uni(st.nnz);
+        const uint64_t nsub = uni64(binom_lookup(pl.binom, nnz, KS));
+        const uint64_t r0 = uni64((item - d.item_begin) * (uint64_t)pl.chunk);
+        const uint64_t r1 = uni64(min(r0 + (uint64_t)pl.chunk, nsub));
+        if (r0 >= r1) continue;
+        const double* x64 = pl.x64 + d.x_off * P;
+        fc.x64 = x64;
+        fc.nrm = pl.nrm + d.x_off;
+        fc.idx_bits = d.idx_bits;
+        int wbest = kBig;
+        for (uint64_t rb = r0; rb < r1; rb += 64) {
+            const uint64_t myr = rb + (uint64_t)lane;
+            Slot& my = slots[lane];
+            if (myr < r1) {
+                int cc[KS > 0 ? KS : 1];
+                cc[0] = 0;
+                unrank_colex<KS>(pl.binom, myr, nnz, cc);
+                double A[P][KS > 0 ? KS : 1];
+#pragma unroll
+                for (int col = 0; col < KS; ++col)
+#pragma unroll
+                    for (int r = 0; r < P; ++r) A[r][col] = x64[(size_t)cc[col] * P + r];
+                Basis<P> Bs;
+                build_basis<P>(A, Bs);
+#pragma unroll
+                for (int col = 0; col < KS; ++col) my.mem[col] = (int16_t)cc[col];
+                if constexpr (TIER == kPlain) {
+                    SlotPlain<P>& S = reinterpret_cast<SlotPlain<P>&>(my);
+#pragma unroll
+                    for (int c = 0; c < P; ++c) { S.e1[c] = Bs.e1[c]; S.e2[c] = Bs.e2[c]; }
+                    S.state = Bs.anynz ? 0 : 1;
+                } else {
+                    SlotFilt<P>& S = reinterpret_cast<SlotFilt<P>&>(my);
+                    SlotF64<P>& S64 = slots64[lane];
+#pragma unroll
+                    for (int c = 0; c < P; ++c) {
+                        S64.e1[c] = Bs.e1[c];
+                        S64.e2[c] = Bs.e2[c];
+                        S.f1[c] = (float)Bs.e1[c];
+                        S.f2[c] = (float)Bs.e2[c];
+                    }
+                    S.beta32 = (float)((((double)P + 3.0) * (double)kU32 + 2.0 * kU64 + Bs.eta) * 1.01);
+                    S64.beta64 = (((double)P + 3.0) * kU64 + Bs.eta) * 1.01;
+                    S.state = (Bs.certified && !pl.force_exact) ? 0 : 3;
+                }
+            } else {
+                my.state = 1;
+            }
+            __syncthreads();
+            // points of the query in registers for the sweeps of this batch
+            // (reloaded per batch so that they are not live while bases are built)
+            if constexpr (TIER == kPlain) {
+#pragma unroll
+                for (int i = 0; i < K; ++i)
+#pragma unroll
+                    for (int c = 0; c < P; ++c) xd[TIER == kPlain ? i : 0][c] = x64[(size_t)(lane * K + i) * P + c];
+            } else {
+                const float* x32 = pl.x32 + d.x_off * P;
+                const float* nrm = pl.nrm + d.x_off;
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+#pragma unroll
+                    for (int c = 0; c < P; ++c) xf[TIER == kPlain ? 0 : i][c] = x32[(size_t)(lane * K + i) * P + c];
+                    nr[TIER == kPlain ? 0 : i] = nrm[lane * K + i];
+                }
+            }
+            const int cnt = (int)min((uint64_t)64, r1 - rb);
+            for (int s = 0; s < cnt; ++s) {
+                const Slot& S = slots[s];
+                const int sstate = uni(S.state);
+                if (sstate == 1) { ++ninvalid; continue; }
+                int term;
+                if constexpr (TIER == kPlain) {
+                    term = sweep_plain<P, K>(xd, reinterpret_cast<const SlotPlain<P>&>(S), nnz);
+                } else {
+                    if (sstate == 3) {
+                        term = kDefer;
+                    } else {
+                        term = sweep_filt<P, K>(xf, nr, reinterpret_cast<const SlotFilt<P>&>(S), slots64[s], nnz, fc,
+                                                side, sg, rechecks);
+                    }
+                }
+                if (term == kDefer) {
+                    if (lane == 0) push_deferred<P>(pl, q, rb + (uint64_t)s);
+                    ++ndefer;
+                    continue;
+                }
+                ++swept;
+                wbest = min(wbest, term);
+            }
+            __syncthreads();
+        }
+        if (lane == 0 && wbest < kBig) atomicMin(&pl.qs[q].min_term, wbest);
+    }
+    // counters (ninvalid counts subsets seen as invalid by the float64 basis)
+    unsigned long long rc = rechecks;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) rc += __shfl_xor(rc, o, 64);
+    if (lane == 0) {
+        if (swept) atomicAdd(&pl.ctr->swept, swept);
+        if (rc) atomicAdd(&pl.ctr->fp64_rechecks, rc);
+        if (ndefer) atomicAdd(&pl.ctr->deferred, ndefer);
+        if (ninvalid) atomicAdd(&pl.ctr->invalid, ninvalid);
+    }
+}
+
+}  // namespace td

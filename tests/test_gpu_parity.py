@@ -1,0 +1,95 @@
+"""Parity of the HIP path with the CPU oracle (element by element, bit-exact).
+
+Stored expected values come from tests/golden/make_golden.py (oracle only);
+small cases are checked against the oracle computed live.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from conftest import to_dev
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+PRECS = ["plain", "filtered"]
+
+
+def golden(cfg):
+    with open(os.path.join(GOLD, cfg + ".json")) as f:
+        return json.load(f)
+
+
+def run(td, dev, X, Z, **kw):
+    c = td.depth(to_dev(X, dev), to_dev(np.atleast_2d(Z), dev), **kw)
+    return c.cpu().numpy().astype(np.int64)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_c1_golden(td, dev, prec):
+    X, Z = workloads.c1()
+    g = golden("c1")
+    exp = np.array([g["counts"][str(q)] for q in range(Z.shape[0])])
+    got = run(td, dev, X, Z, precision=prec)
+    print("c1", prec, got.tolist())
+    assert np.array_equal(got, exp)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_c2_golden(td, dev, prec):
+    X, Z = workloads.c2()
+    g = golden("c2")
+    qs = sorted(int(k) for k in g["counts"])
+    exp = np.array([g["counts"][str(q)] for q in qs])
+    got = run(td, dev, X, Z[qs], precision=prec)
+    st = td.get_stats()
+    print("c2", prec, "mismatches", int(np.sum(got != exp)), st)
+    assert np.array_equal(got, exp)
+
+
+def _grid_cases():
+    rng = np.random.default_rng(11)
+    cases = []
+    for p in range(2, 7):
+        for n in sorted(set([p + 1, p + 3, 17, 40, 64, 65, 100])):
+            if p >= 6 and n > 40:
+                continue
+            cases.append((p, n, int(rng.integers(0, 2**31))))
+    return cases
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("p,n,seed", _grid_cases())
+def test_random_grid(td, dev, prec, p, n, seed):
+    """Gaussian data of many sizes: several tiles and ragged tails, queries
+    inside and outside the cloud and on a sample point."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, p))
+    Z = np.vstack([rng.standard_normal((3, p)), 3.0 * rng.standard_normal((1, p)), X[:1]])
+    exp = oracle.depth_counts(X, Z)
+    got = run(td, dev, X, Z, precision=prec)
+    assert np.array_equal(got, exp), (got, exp)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_symmetric_closed_form(td, dev, prec):
+    """{z +- v_k}: the depth count is exactly k (plus 1 with z itself)."""
+    rng = np.random.default_rng(5)
+    for p, k in [(3, 150), (4, 120), (5, 100), (6, 30)]:
+        for center in (False, True):
+            X, Z = workloads.symmetric(rng, p, k, with_center=center)
+            got = run(td, dev, X, Z, precision=prec)
+            assert got[0] == k + (1 if center else 0), (p, k, center, got)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_outside_hull_zero(td, dev, prec):
+    rng = np.random.default_rng(9)
+    for p in (2, 3, 4, 5):
+        X = rng.standard_normal((120, p))
+        z = workloads.outside_hull_query(X, rng)
+        assert run(td, dev, X, z, precision=prec)[0] == 0
