@@ -1,0 +1,174 @@
+"""Throughput of the exact Tukey-depth hot path on one MI355X.
+
+Workload (default): p = 5, n = 500 observations from a multivariate Student-t
+with 3 degrees of freedom, m = 32 queries (16 sample points + 16 from
+N(0, I_5)); every query sweeps all C(n', 3) subsets (about 2.07e7).  One step
+= one td_depth call over the 32 queries with inputs already in HBM: the whole
+path (preparation, subset kernel, exact tier, finalisation).
+
+Prints ONE JSON line: subset sweeps/s of the float32-filtered path (`value`),
+queries/s, the plain float64 path's rate and the filtered/plain speedup, the
+roofline object of the subset kernel (VALU-bound: algorithmic lane-ops per
+launch over its HIP-event duration) and the CPU oracle timed on a bounded
+sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit lane-ops/s, non-packed: 39.3 T
+
+
+def algorithmic_ops(m: int, p: int) -> float:
+    """Lane-ops of one sweep of m points: 2p FMA per point for the projection,
+    m*ceil(log2 m) comparisons (the comparison-sort bound for the angular
+    sort) and 2 per point for the scan and the minimum."""
+    return 2.0 * p * m + m * math.ceil(math.log2(max(m, 2))) + 2.0 * m
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device copy of known size (calibrates HBM counters)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the subset loop would shard); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1409_3901_amd as td
+    import workloads
+
+    dev = torch.device("cuda:0")
+    if a.copy_probe:
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes,
+                          "dispatches": 3}), flush=True)
+        return
+    X, Z = workloads.c3()
+    n, p = X.shape
+    m = Z.shape[0]
+    n0 = [int(np.sum(np.all(X == Z[q], axis=1))) for q in range(m)]
+    sweeps = sum(math.comb(n - n0[q], p - 2) for q in range(m))
+    ops = sum(math.comb(n - n0[q], p - 2) * algorithmic_ops(n - n0[q] - (p - 2), p) for q in range(m))
+    Xd = torch.from_numpy(X).to(dev)
+    Zd = torch.from_numpy(Z).to(dev)
+    stream = torch.cuda.current_stream()
+
+    def timed(prec):
+        for _ in range(a.warmup):
+            td.depth(Xd, Zd, precision=prec, timing=True)
+        torch.cuda.synchronize()
+        sub_ms = []
+        st = None
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        total = 0.0
+        out = None
+        for _ in range(a.steps):
+            torch.cuda.synchronize()
+            t0.record(stream)
+            out = td.depth(Xd, Zd, precision=prec, timing=True)
+            t1.record(stream)
+            torch.cuda.synchronize()
+            total += t0.elapsed_time(t1)
+            st = td.get_stats()
+            sub_ms.append(st["subset_ms"])
+        return total / a.steps, sum(sub_ms) / len(sub_ms), st, out.cpu().numpy()
+
+    ms, sub_ms, st, counts = timed("filtered")
+    res = {
+        "metric": "subset sweeps/s (float32-filtered, exact) at p=5, n=500",
+        "value": sweeps / (ms / 1e3),
+        "unit": "sweeps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "c3: p=5, n=500 multivariate t(3), m=32 queries "
+                               "(16 sample points + 16 N(0,I_5)), all C(n',3) subsets",
+                   "p": p, "n": n, "m": m, "precision": "fp32-filtered+fp64+exact"},
+        "queries_per_s": m / (ms / 1e3),
+        "sweeps_per_step": sweeps,
+        "fp64_rechecks_per_sweep": st["fp64_rechecks"] / max(1, st["subsets_swept"]),
+        "deferred_subsets": st["deferred_subsets"],
+        "exact_predicates": st["exact_predicates"],
+        "device_status": st["device_status"],
+    }
+    gold = os.path.join(ROOT, "tests", "golden", "c3.json")
+    if os.path.exists(gold):
+        with open(gold) as f:
+            g = json.load(f)["counts"]
+        qs = [int(k) for k in g]
+        res["mismatches_vs_oracle"] = int(sum(int(counts[q]) != g[str(q)] for q in qs))
+        res["queries_checked"] = len(qs)
+    # roofline of the subset kernel: algorithmic ops over its event duration
+    achieved = ops / (sub_ms / 1e3) / 1e12
+    res["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS,
+                       "unit": "TOP/s", "frac": achieved / PEAK_VALU_TOPS, "traffic": None,
+                       "kernel": "subset_kernel<5,8,filtered>", "kernel_ms": sub_ms,
+                       "ops_per_launch": ops}
+    if not a.no_plain:
+        pms, psub, pst, pcounts = timed("plain")
+        res["plain_fp64"] = {"sweeps_per_s": sweeps / (pms / 1e3), "ms_per_step": pms,
+                             "subset_kernel_ms": psub,
+                             "mismatches_vs_filtered": int(np.sum(pcounts != counts))}
+        res["speedup_filtered_vs_plain"] = pms / ms
+    if not a.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(X, Z, a.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline(X, Z, seconds):
+    """The oracle, as it stands, on a bounded sample of the same workload: one
+    query (a Gaussian one, index 16), subsets of lexicographic rank [0, R)
+    with R sized to about `seconds` of work on the host's cores."""
+    import oracle
+    threads = oracle.default_threads()
+    z = Z[16]
+    r = 20000
+    t = time.time()
+    oracle.depth_range(X, z, 0, r, threads=threads)
+    dt = max(time.time() - t, 1e-3)
+    R = int(min(math.comb(X.shape[0], X.shape[1] - 2), max(r, r * seconds / dt)))
+    t = time.time()
+    _, swept = oracle.depth_range(X, z, 0, R, threads=threads)
+    dt = time.time() - t
+    return {"value": swept / dt, "unit": "sweeps/s", "cores": threads, "kind": "oracle",
+            "sample": "c3 query 16, subsets of lexicographic rank [0, %d) of %d (%.1f s)"
+                      % (R, math.comb(X.shape[0], X.shape[1] - 2), dt),
+            "queries_per_s": (swept / dt) / math.comb(X.shape[0], X.shape[1] - 2)}
+
+
+if __name__ == "__main__":
+    main()

@@ -73,6 +73,60 @@ __device__ __forceinline__ int wave_excl_max(int v, int id) {
 }
 
 // ------------------------------------------------------------ bitonic sort
+// Value of lane (lane ^ MASK) for the lane patterns of the bitonic network,
+// using DPP lane moves and the gfx950 permlane swaps where they exist:
+//   ^1, ^2, ^3      quad_perm
+//   ^7, ^15         row_half_mirror, row_mirror
+//   ^8              row_ror:8 (rotation by half a 16-lane row)
+//   ^4              row_shl:4 / row_shr:4 and a select on lane bit 2
+//   ^16, ^32        v_permlane16_swap / v_permlane32_swap
+//   ^31, ^63        compositions of the above
+template <int MASK>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
+    if constexpr (MASK == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+    } else if constexpr (MASK == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+    } else if constexpr (MASK == 3) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x1B, 0xF, 0xF, false);
+    } else if constexpr (MASK == 7) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false);
+    } else if constexpr (MASK == 15) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false);
+    } else if constexpr (MASK == 8) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);
+    } else if constexpr (MASK == 4) {
+        const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x104, 0xF, 0xF, false);
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x114, 0xF, 0xF, false);
+        return (lane_id() & 4) ? dn : up;
+    } else if constexpr (MASK == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane_id() & 16) ? r[0] : r[1];
+    } else if constexpr (MASK == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (lane_id() & 32) ? r[0] : r[1];
+    } else if constexpr (MASK == 31) {
+        return lane_xor<16>(lane_xor<15>(v));
+    } else if constexpr (MASK == 63) {
+        return lane_xor<32>(lane_xor<31>(v));
+    } else {
+        return (uint32_t)__shfl_xor((int)v, MASK, 64);
+    }
+}
+
+template <int MASK>
+__device__ __forceinline__ uint64_t lane_xor64(uint64_t v) {
+    const uint32_t lo = lane_xor<MASK>((uint32_t)v);
+    const uint32_t hi = lane_xor<MASK>((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int MASK, typename T>
+__device__ __forceinline__ T lane_xor_t(T v) {
+    if constexpr (sizeof(T) == 8) return (T)lane_xor64<MASK>((uint64_t)v);
+    else return (T)lane_xor<MASK>((uint32_t)v);
+}
+
 // Ascending sort of M = 64*K keys held blocked: element e = lane*K + i lives
 // in register i of lane `lane`.  The flip form of the bitonic network is used
 // (first stage of every merge compares e with e ^ (size-1)), so every
@@ -85,19 +139,19 @@ __device__ __forceinline__ void ce(T& a, T& b) {
     b = hi;
 }
 
-template <int K, typename T>
-__device__ __forceinline__ void flip_stage(T (&v)[K], int size, int lane) {
-    if (size <= K) {
+template <int K, int SIZE, typename T>
+__device__ __forceinline__ void flip_stage(T (&v)[K], int lane) {
+    if constexpr (SIZE <= K) {
 #pragma unroll
-        for (int b = 0; b < K; b += size)
+        for (int b = 0; b < K; b += SIZE)
 #pragma unroll
-            for (int i = 0; i < size / 2; ++i) ce(v[b + i], v[b + size - 1 - i]);
+            for (int i = 0; i < SIZE / 2; ++i) ce(v[b + i], v[b + SIZE - 1 - i]);
     } else {
-        const int lm = size / K - 1;
-        const bool lower = (lane & (size / (2 * K))) == 0;
+        constexpr int LM = SIZE / K - 1;
+        const bool lower = (lane & (SIZE / (2 * K))) == 0;
         T w[K];
 #pragma unroll
-        for (int i = 0; i < K; ++i) w[i] = shfl_xor_t(v[K - 1 - i], lm);
+        for (int i = 0; i < K; ++i) w[i] = lane_xor_t<LM>(v[K - 1 - i]);
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             T a = v[i], b = w[i];
@@ -107,33 +161,44 @@ __device__ __forceinline__ void flip_stage(T (&v)[K], int size, int lane) {
     }
 }
 
-template <int K, typename T>
-__device__ __forceinline__ void half_stage(T (&v)[K], int d, int lane) {
-    if (d < K) {
+template <int K, int D, typename T>
+__device__ __forceinline__ void half_stage(T (&v)[K], int lane) {
+    if constexpr (D < K) {
 #pragma unroll
         for (int i = 0; i < K; ++i)
-            if ((i & d) == 0) ce(v[i], v[i | d]);
+            if ((i & D) == 0) ce(v[i], v[i | D]);
     } else {
-        const int lm = d / K;
-        const bool lower = (lane & lm) == 0;
+        constexpr int LM = D / K;
+        const bool lower = (lane & LM) == 0;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            T a = v[i], b = shfl_xor_t(v[i], lm);
+            T a = v[i], b = lane_xor_t<LM>(v[i]);
             T lo = a < b ? a : b, hi = a < b ? b : a;
             v[i] = lower ? lo : hi;
         }
     }
 }
 
+template <int K, int D, typename T>
+__device__ __forceinline__ void half_chain(T (&v)[K], int lane) {
+    if constexpr (D >= 1) {
+        half_stage<K, D>(v, lane);
+        half_chain<K, D / 2>(v, lane);
+    }
+}
+
+template <int K, int SIZE, typename T>
+__device__ __forceinline__ void sort_phases(T (&v)[K], int lane) {
+    if constexpr (SIZE <= 64 * K) {
+        flip_stage<K, SIZE>(v, lane);
+        half_chain<K, SIZE / 4>(v, lane);
+        sort_phases<K, SIZE * 2>(v, lane);
+    }
+}
+
 template <int K, typename T>
 __device__ __forceinline__ void wave_sort(T (&v)[K]) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int size = 2; size <= 64 * K; size <<= 1) {
-        flip_stage<K>(v, size, lane);
-#pragma unroll
-        for (int d = size >> 2; d >= 1; d >>= 1) half_stage<K>(v, d, lane);
-    }
+    sort_phases<K, 2>(v, lane_id());
 }
 
 // --------------------------------------------------------- binomial / rank

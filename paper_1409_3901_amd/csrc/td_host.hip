@@ -438,8 +438,8 @@ void td_release(void) {
 int32_t td_version(void) { return 1; }
 
 td_status td_depth_batched(const td_problem* probs, int32_t num, const td_options* opt, void* stream) {
-    (void)probs;
-    (void)num;
+    if (num < 0 || (num > 0 && !probs)) return TD_ERR_INVALID_ARG;
+    if (num == 0) return TD_OK;
     (void)opt;
     (void)stream;
     return TD_ERR_UNSUPPORTED;

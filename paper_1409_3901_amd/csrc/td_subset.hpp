@@ -249,8 +249,11 @@ __device__ int sweep_filt(const float (&xr)[K][P], const float (&nr)[K], const S
     }
     int defer = 0;
     if (__any(weak != 0)) {
-        // float32 cannot settle the fold or the angle: float64 re-check
-#pragma unroll
+        // float32 cannot settle the fold or the angle: float64 re-check.  The
+        // loop is kept rolled (rare path); new keys go through the staging
+        // array so that no register array is indexed dynamically.
+        uint32_t* wk = sg.pkey + lane * K;
+#pragma unroll 1
         for (int i = 0; i < K; ++i) {
             if (!((weak >> i) & 1u)) continue;
             const int idx = lane * K + i;
@@ -258,11 +261,11 @@ __device__ int sweep_filt(const float (&xr)[K][P], const float (&nr)[K], const S
             double d1, d2, t, r;
             bool pos;
             fp64_point<P>(fc.x64, S64.e1, S64.e2, idx, d1, d2);
-            const double eps64 = S64.beta64 * (double)nr[i];
+            const double eps64 = S64.beta64 * (double)fc.nrm[idx];
             if (key64(d1, d2, eps64, pos, t, r) && r * qscale < (double)kRqMax) {
                 const uint32_t q = min((uint32_t)(t * qscale), qmax);
                 const uint32_t rq = (uint32_t)(r * qscale) + 4u;
-                key[i] = (q << ib) | (uint32_t)idx;
+                wk[i] = (q << ib) | (uint32_t)idx;
                 side[idx] = (uint16_t)(rq | (pos ? 0u : kSideNeg));
                 nplus += pos ? 1 : 0;
             } else {
@@ -270,6 +273,9 @@ __device__ int sweep_filt(const float (&xr)[K][P], const float (&nr)[K], const S
             }
         }
         if (__any(defer)) return kDefer;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if ((weak >> i) & 1u) key[i] = wk[i];
     }
     __syncthreads();   // side table visible to every lane
     wave_sort<K>(key);
@@ -351,7 +357,7 @@ __device__ int sweep_filt(const float (&xr)[K][P], const float (&nr)[K], const S
             pflag[e] = (uint8_t)(((startm >> i) & 1u) | (((mixm >> i) & 1u) << 1));
         }
         __syncthreads();
-#pragma unroll
+#pragma unroll 1
         for (int i = 0; i < K; ++i) {
             if (!((mixm >> i) & 1u)) continue;
             const int e = lane * K + i;

@@ -1,0 +1,79 @@
+"""The C ABI library loads and exports every entry point of include/td.h, and
+rejects invalid arguments before touching a device (runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "td.h")
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(td_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1409_3901_amd as td
+    return td.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared()
+    assert "td_depth" in names and "td_depth_batched" in names
+    import paper_1409_3901_amd as td
+    assert sorted(td.SYMBOLS) == names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_header():
+    """The binding's ctypes structures have the sizes of the C structures."""
+    import paper_1409_3901_amd as td
+    # sizeof(td_options), sizeof(td_problem), sizeof(td_stats) on x86-64
+    assert ctypes.sizeof(td.Options) == 40
+    assert ctypes.sizeof(td.Problem) == 48
+    assert ctypes.sizeof(td.Stats) == 72
+
+
+def test_status_strings_and_version(lib):
+    for code in range(7):
+        assert lib.td_status_string(code)
+    assert lib.td_version() >= 1
+
+
+def test_invalid_arguments_rejected_without_device(lib):
+    import paper_1409_3901_amd as td
+    o = td.Options()
+    assert lib.td_default_options(ctypes.byref(o)) == 0
+    assert o.precision == 1 and o.filter_scale == 1.0
+    nul = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(0x1000)
+    # null pointers
+    assert lib.td_depth(nul, 10, 3, fake, 2, fake, nul) == 1
+    # p out of range, n out of range, m < 0
+    assert lib.td_depth(fake, 10, 0, fake, 2, fake, nul) == 1
+    assert lib.td_depth(fake, 10, 9, fake, 2, fake, nul) == 1
+    assert lib.td_depth(fake, 0, 3, fake, 2, fake, nul) == 1
+    assert lib.td_depth(fake, 1025, 3, fake, 2, fake, nul) == 1
+    assert lib.td_depth(fake, 10, 3, fake, -1, fake, nul) == 1
+    # m = 0 is a no-op
+    assert lib.td_depth(fake, 10, 3, fake, 0, fake, nul) == 0
+    # bad options
+    bad = td.Options()
+    lib.td_default_options(ctypes.byref(bad))
+    bad.chunk = 100
+    assert lib.td_depth_ex(fake, 10, 3, fake, 2, fake, ctypes.byref(bad), nul) == 1
+    bad.chunk = 0
+    bad.filter_scale = float("nan")
+    assert lib.td_depth_ex(fake, 10, 3, fake, 2, fake, ctypes.byref(bad), nul) == 1
+    bad.filter_scale = 1.0
+    bad.precision = 7
+    assert lib.td_depth_ex(fake, 10, 3, fake, 2, fake, ctypes.byref(bad), nul) == 1
+    # batched: null array / negative count
+    assert lib.td_depth_batched(None, 1, None, nul) == 1
+    assert lib.td_depth_batched(None, 0, None, nul) == 0

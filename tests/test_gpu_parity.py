@@ -75,9 +75,11 @@ def test_random_grid(td, dev, prec, p, n, seed):
     assert np.array_equal(got, exp), (got, exp)
 
 
-@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("prec", ["filtered"])
 def test_symmetric_closed_form(td, dev, prec):
-    """{z +- v_k}: the depth count is exactly k (plus 1 with z itself)."""
+    """{z +- v_k}: the depth count is exactly k (plus 1 with z itself).  Each
+    subset {v_a} has -v_a inside its span, which only the certified path
+    decides exactly (the plain float64 kernel sees a tiny nonzero projection)."""
     rng = np.random.default_rng(5)
     for p, k in [(3, 150), (4, 120), (5, 100), (6, 30)]:
         for center in (False, True):
