@@ -139,6 +139,25 @@ __device__ __forceinline__ void ce(T& a, T& b) {
     b = hi;
 }
 
+// Median of three unsigned words.  With c = 0 it is min(a, b), with c = ~0 it
+// is max(a, b): one instruction for a cross-lane compare-exchange whose
+// direction depends on the lane.
+__device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ T cx_pick(T a, T b, bool lower) {
+    if constexpr (sizeof(T) == 4) {
+        return (T)med3u((uint32_t)a, (uint32_t)b, lower ? 0u : 0xffffffffu);
+    } else {
+        T lo = a < b ? a : b, hi = a < b ? b : a;
+        return lower ? lo : hi;
+    }
+}
+
 template <int K, int SIZE, typename T>
 __device__ __forceinline__ void flip_stage(T (&v)[K], int lane) {
     if constexpr (SIZE <= K) {
@@ -153,11 +172,7 @@ __device__ __forceinline__ void flip_stage(T (&v)[K], int lane) {
 #pragma unroll
         for (int i = 0; i < K; ++i) w[i] = lane_xor_t<LM>(v[K - 1 - i]);
 #pragma unroll
-        for (int i = 0; i < K; ++i) {
-            T a = v[i], b = w[i];
-            T lo = a < b ? a : b, hi = a < b ? b : a;
-            v[i] = lower ? lo : hi;
-        }
+        for (int i = 0; i < K; ++i) v[i] = cx_pick(v[i], w[i], lower);
     }
 }
 
@@ -170,11 +185,24 @@ __device__ __forceinline__ void half_stage(T (&v)[K], int lane) {
     } else {
         constexpr int LM = D / K;
         const bool lower = (lane & LM) == 0;
+        if constexpr (sizeof(T) == 4 && (LM == 16 || LM == 32)) {
+            // The swap hands every lane (own, partner) or (partner, own);
+            // the median with 0 / ~0 picks min / max either way.
+            const uint32_t sel = lower ? 0u : 0xffffffffu;
 #pragma unroll
-        for (int i = 0; i < K; ++i) {
-            T a = v[i], b = lane_xor_t<LM>(v[i]);
-            T lo = a < b ? a : b, hi = a < b ? b : a;
-            v[i] = lower ? lo : hi;
+            for (int i = 0; i < K; ++i) {
+                const uint32_t x = (uint32_t)v[i];
+                if constexpr (LM == 16) {
+                    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+                    v[i] = (T)med3u(r[0], r[1], sel);
+                } else {
+                    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+                    v[i] = (T)med3u(r[0], r[1], sel);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < K; ++i) v[i] = cx_pick(v[i], lane_xor_t<LM>(v[i]), lower);
         }
     }
 }

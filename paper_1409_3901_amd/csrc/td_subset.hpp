@@ -223,29 +223,26 @@ __device__ int sweep_filt(const float (&xr)[K][P], const float (&nr)[K], const S
         // is strictly increasing with the angle on that half-plane.  With the
         // float32 error eps of each coordinate the key error is at most
         // eps / (s - 2 eps) plus the rounding of t' (Algorithm 2, Step 1(b)).
+        // Branch-free: invalid and uncertain points are masked afterwards.
         const float eps = beta * nr[i];
         const bool pos = y1 > 0.0f;
         const float h1 = fabsf(y1);
         const float h2 = pos ? y2 : -y2;
         const float s = h1 + fabsf(h2);
-        // __fdividef is within 2 ulp: covered by the 8 u32 term and the 1.001
-        const float t = __fdividef(h2, s) + 1.0f;
-        const float r = __fdividef(eps, s - 2.0f * eps) * 1.001f + 8.0f * kU32;
+        // hardware reciprocals are within 1 ulp: covered by the 8 u32 term
+        // and the factor 1.001
+        const float t = h2 * __builtin_amdgcn_rcpf(s) + 1.0f;
+        const float r = eps * __builtin_amdgcn_rcpf(s - 2.0f * eps) * 1.001f + 8.0f * kU32;
         const float rqf = r * qscalef;
         const bool ok = (h1 > eps) && (s > 4.0f * eps) && (rqf < (float)kRqMax);
-        uint32_t kk = 0xffffffffu;
-        if (valid) {
-            if (ok) {
-                const uint32_t q = min((uint32_t)(t * qscalef), qmax);
-                const uint32_t rq = (uint32_t)rqf + 4u;
-                kk = (q << ib) | (uint32_t)idx;
-                side[idx] = (uint16_t)(rq | (pos ? 0u : kSideNeg));
-                nplus += pos ? 1 : 0;
-            } else {
-                weak |= 1u << i;
-            }
-        }
-        key[i] = kk;
+        const uint32_t q = min((uint32_t)(t * qscalef), qmax);
+        const uint32_t rq = ok ? (uint32_t)rqf + 4u : 0u;
+        // idx < M always: the side entry of a point that is not swept is
+        // written but never read
+        side[idx] = (uint16_t)(rq | (pos ? 0u : kSideNeg));
+        key[i] = (valid && ok) ? ((q << ib) | (uint32_t)idx) : 0xffffffffu;
+        weak |= (valid && !ok) ? (1u << i) : 0u;
+        nplus += (valid && ok && pos) ? 1 : 0;
     }
     int defer = 0;
     if (__any(weak != 0)) {
@@ -285,11 +282,10 @@ __device__ int sweep_filt(const float (&xr)[K][P], const float (&nr)[K], const S
     int loc = 0, lmax = -kBig;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        if (key[i] != 0xffffffffu) {
-            const uint32_t sd = side[key[i] & imask];
-            loc += (sd & kSideNeg) ? 1 : -1;
-            lmax = max(lmax, (int)(key[i] >> ib) + (int)(sd & 0x7fffu));
-        }
+        const bool real = key[i] != 0xffffffffu;
+        const uint32_t sd = side[key[i] & imask];   // in bounds for pads too
+        loc += real ? ((sd & kSideNeg) ? 1 : -1) : 0;
+        lmax = real ? max(lmax, (int)(key[i] >> ib) + (int)(sd & 0x7fffu)) : lmax;
     }
     const int pm0 = wave_excl_max(lmax, -kBig);
     const int s0 = S0 + wave_excl_sum(loc);
@@ -305,23 +301,20 @@ __device__ int sweep_filt(const float (&xr)[K][P], const float (&nr)[K], const S
     // delta of the element before this lane's first one
     int dl_before;
     {
-        int dl_last_lane = 0;
-        if (key[K - 1] != 0xffffffffu) dl_last_lane = (side[key[K - 1] & imask] & kSideNeg) ? 1 : -1;
+        const uint32_t sdl = side[key[K - 1] & imask];
+        const int dl_last_lane = (key[K - 1] != 0xffffffffu) ? ((sdl & kSideNeg) ? 1 : -1) : 0;
         dl_before = __shfl_up(dl_last_lane, 1, 64);
     }
     int dp = dl_before;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const bool real = key[i] != 0xffffffffu;
-        int dl = 0, lo = kBig, hi = -kBig;
-        if (real) {
-            const uint32_t sd = side[key[i] & imask];
-            const int rq = (int)(sd & 0x7fffu);
-            const int qv = (int)(key[i] >> ib);
-            dl = (sd & kSideNeg) ? 1 : -1;
-            lo = qv - rq;
-            hi = qv + rq;
-        }
+        const uint32_t sd = side[key[i] & imask];
+        const int rq = (int)(sd & 0x7fffu);
+        const int qv = (int)(key[i] >> ib);
+        const int dl = real ? ((sd & kSideNeg) ? 1 : -1) : 0;
+        const int lo = real ? qv - rq : kBig;
+        const int hi = real ? qv + rq : -kBig;
         const bool st = real && lo > pm;
         pm = max(pm, hi);
         if (st) startm |= 1u << i;
@@ -525,16 +518,21 @@ __global__ __launch_bounds__(64) void subset_kernel(Pools pl) {
                 my.state = 1;
             }
             __syncthreads();
-            // points of the query in registers for the sweeps of this batch
-            // (reloaded per batch so that they are not live while bases are built)
+            // points of the query in registers for the sweeps of this batch,
+            // reloaded per batch so that they are not live while bases are
+            // built: an opaque zero (a volatile scalar move, no memory access)
+            // keeps the loop-invariant loads from being hoisted out of the loop
+            uint32_t opaque;
+            asm volatile("s_mov_b32 %0, 0" : "=s"(opaque));
             if constexpr (TIER == kPlain) {
+                const double* xb = x64 + opaque;
 #pragma unroll
                 for (int i = 0; i < K; ++i)
 #pragma unroll
-                    for (int c = 0; c < P; ++c) xd[TIER == kPlain ? i : 0][c] = x64[(size_t)(lane * K + i) * P + c];
+                    for (int c = 0; c < P; ++c) xd[TIER == kPlain ? i : 0][c] = xb[(size_t)(lane * K + i) * P + c];
             } else {
-                const float* x32 = pl.x32 + d.x_off * P;
-                const float* nrm = pl.nrm + d.x_off;
+                const float* x32 = pl.x32 + d.x_off * P + opaque;
+                const float* nrm = pl.nrm + d.x_off + opaque;
 #pragma unroll
                 for (int i = 0; i < K; ++i) {
 #pragma unroll
