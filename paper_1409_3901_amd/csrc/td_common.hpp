@@ -37,7 +37,8 @@ struct QueryDesc {
     int32_t n, p;
     int32_t M;          // sort width: power of two >= n - (p-2), >= 64
     int32_t idx_bits;   // bits of the point index inside a 32-bit key
-    uint64_t x_off;     // offset (elements) of this query's arrays in the pools
+    uint64_t v_off;     // offset (values) of this query's x64 / x32 arrays
+    uint64_t n_off;     // offset (points) of this query's nrm array
     uint64_t item_begin;// first global work item of this query
     uint32_t items;     // work items of this query
     int32_t cls;        // (p, K) class index for the batched dispatcher
@@ -50,7 +51,9 @@ struct Deferred {
     uint64_t rank;
 };
 
-// Device counters accumulated per call.
+constexpr int kMaxClasses = 40;   // (p, K) classes of one call
+
+// Device counters accumulated per call (cleared by the init kernel).
 struct Counters {
     unsigned long long swept;
     unsigned long long fp64_rechecks;
@@ -58,16 +61,23 @@ struct Counters {
     unsigned long long exact_preds;
     unsigned long long degenerate;
     unsigned long long invalid;
-    unsigned long long work_next;     // work-item counter of the subset kernels
     unsigned long long defer_next;    // deferred-queue write position
-    unsigned long long exact_next;    // deferred-queue read position
     unsigned long long prep_next;     // query counter of the preparation kernel
-    unsigned long long fin_next;      // query counter of the finalisation
-    unsigned long long pad[5];
+    unsigned long long work_next[kMaxClasses];   // work-item counter per class
 };
 
-// Pools of per-query arrays (offsets in QueryDesc::x_off, in points*p units
-// for the AoS arrays and points for nrm).
+// Per-call parameters in device memory, so that the kernel arguments (and a
+// captured graph) do not change from call to call.
+struct CallParams {
+    int32_t num_queries;
+    int32_t num_classes;
+    uint64_t cls_begin[kMaxClasses];  // global work items [begin, end) per class
+    uint64_t cls_end[kMaxClasses];
+    uint64_t cls_scratch[kMaxClasses];// byte offset of the class's block scratch
+};
+
+// Pools of per-query arrays (offsets QueryDesc::v_off in values for the AoS
+// arrays, xi at 2 * v_off; QueryDesc::n_off in points for nrm).
 struct Pools {
     double* x64;        // centred points, float64, AoS [M][p]
     float* x32;         // centred points, float32, AoS [M][p]
@@ -77,14 +87,14 @@ struct Pools {
     const uint64_t* binom;  // binomial table [kBinomN][kBinomK]
     QueryState* qs;
     const QueryDesc* qd;
+    const CallParams* cp;
     Deferred* deferred;
     Counters* ctr;
     uint64_t defer_cap;
-    uint64_t total_items;
-    int32_t num_queries;
     int32_t chunk;      // subsets per work item (multiple of 64)
     float filter_scale;
     int32_t force_exact;
+    int32_t cls;        // class slot of this launch (subset and exact kernels)
     uint8_t* wscratch;       // per-block scratch in device memory
     uint64_t wscratch_bytes; // bytes per block
 };

@@ -284,27 +284,27 @@ __global__ __launch_bounds__(64) void exact_kernel(Pools pl) {
     __shared__ int s_nextra;
     __shared__ int s_flag;
     const int lane = lane_id();
-    ExactScratch<P>* X = reinterpret_cast<ExactScratch<P>*>(pl.wscratch + (uint64_t)blockIdx.x * pl.wscratch_bytes);
+    ExactScratch<P>* X = reinterpret_cast<ExactScratch<P>*>(pl.wscratch + pl.cp->cls_scratch[pl.cls] +
+                                                            (uint64_t)blockIdx.x * pl.wscratch_bytes);
     unsigned long long swept = 0, preds = 0, degen = 0, ninvalid = 0;
     const unsigned long long nd = pl.ctr->defer_next;
     const unsigned long long total = nd < pl.defer_cap ? nd : pl.defer_cap;
+    // Static striding over the deferred list: every class launch scans the
+    // whole list and takes the entries of its own class.
+    unsigned long long it = blockIdx.x;
     constexpr double qscale = 4503599627370496.0;     // 2^52: t' in [0,2] -> 53 bits
     constexpr uint64_t qmax = (1ull << 54) - 2ull;
     constexpr uint32_t kWide = 0x3fffffffu;
-    while (true) {
-        unsigned long long it = 0;
-        if (lane == 0) it = atomicAdd(&pl.ctr->exact_next, 1ull);
-        it = uni64(__shfl(it, 0, 64));
-        if (it >= total) break;
+    for (; it < total; it += gridDim.x) {
         const Deferred dfr = pl.deferred[it];
         const int q = uni((int)dfr.query);
         const QueryDesc d = pl.qd[q];
         const QueryState st = pl.qs[q];
         if (d.p != P || d.M != M) continue;   // belongs to another class
         const int nnz = uni(st.nnz);
-        const double* x64 = pl.x64 + d.x_off * P;
-        const float* nrm = pl.nrm + d.x_off;
-        const uint64_t* xi = pl.xi + d.x_off * P * 2;
+        const double* x64 = pl.x64 + d.v_off;
+        const float* nrm = pl.nrm + d.n_off;
+        const uint64_t* xi = pl.xi + d.v_off * 2;
         int mem[KS > 0 ? KS : 1];
         mem[0] = 0;
         unrank_colex<KS>(pl.binom, dfr.rank, nnz, mem);

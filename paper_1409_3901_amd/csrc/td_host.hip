@@ -1,10 +1,16 @@
 // Host side of the C ABI declared in include/td.h.
+//
+// One engine serves td_depth_ex and td_depth_batched.  The queries of a call
+// are grouped by class (p, K): K = sort width / 64, the number of points each
+// lane holds.  Every class gets a contiguous range of work items (a work item
+// is `chunk` consecutive subset ranks of one query) and its own persistent
+// subset kernel; per-call data (query descriptors, class ranges) lives in
+// device memory, so kernel arguments do not change between calls and the
+// whole call can be captured once in a HIP graph and replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <chrono>
 #include <cmath>
-#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -14,8 +20,9 @@
 #include "../../include/td.h"
 #include "td_common.hpp"
 
+extern "C" hipError_t td_launch_init(const td::Pools* pl, hipStream_t s);
 extern "C" hipError_t td_launch_prep(const td::Pools* pl, int blocks, hipStream_t s);
-extern "C" hipError_t td_launch_finalize(const td::Pools* pl, hipStream_t s);
+extern "C" hipError_t td_launch_finalize(const td::Pools* pl, int blocks, hipStream_t s);
 extern "C" hipError_t td_launch_subset_plain(int P, int K, int blocks, hipStream_t s, const td::Pools* pl);
 extern "C" hipError_t td_launch_subset_filt(int P, int K, int blocks, hipStream_t s, const td::Pools* pl);
 extern "C" hipError_t td_launch_exact(int P, int K, int blocks, hipStream_t s, const td::Pools* pl, int all_items);
@@ -23,6 +30,7 @@ extern "C" uint64_t td_exact_scratch_bytes(int P);
 
 namespace {
 
+using td::CallParams;
 using td::Counters;
 using td::Deferred;
 using td::Pools;
@@ -40,9 +48,7 @@ constexpr int64_t kDefaultDeferCap = 1 << 25;
 uint64_t binom_host(int64_t n, int k) {
     if (k < 0 || n < k) return 0;
     unsigned __int128 r = 1;
-    for (int i = 1; i <= k; ++i) {
-        r = r * (unsigned __int128)(n - k + i) / (unsigned __int128)i;
-    }
+    for (int i = 1; i <= k; ++i) r = r * (unsigned __int128)(n - k + i) / (unsigned __int128)i;
     if (r > (unsigned __int128)UINT64_MAX) return UINT64_MAX;
     return (uint64_t)r;
 }
@@ -53,42 +59,61 @@ int next_pow2(int v) {
     return m;
 }
 
-// One workspace per (device, stream): device pools and a pinned staging
-// buffer for the query descriptors.
+struct Problem {
+    const double* X;
+    int64_t n;
+    int32_t p;
+    const double* Z;
+    int64_t m;
+    int32_t* counts;
+};
+
+// Launch shape of one class.
+struct Shape {
+    int chunk = 256;
+    int blocks = 0;   // 0: auto
+};
+
+// Device buffers of one (device, stream) pair.
 struct Workspace {
     int device = -1;
     hipStream_t stream = nullptr;
-    // device buffers
     double* x64 = nullptr;
     float* x32 = nullptr;
-    float* nrm = nullptr;
     uint64_t* xi = nullptr;
-    size_t pts_cap = 0;          // capacity in points*p units
-    size_t nrm_cap = 0;          // capacity in points
+    size_t val_cap = 0;         // values (points * p)
+    float* nrm = nullptr;
+    size_t pts_cap = 0;         // points
     QueryDesc* qd = nullptr;
     QueryState* qs = nullptr;
     size_t q_cap = 0;
+    CallParams* cp = nullptr;
     Deferred* deferred = nullptr;
     int64_t defer_cap = 0;
     Counters* ctr = nullptr;
-    uint8_t* wscratch = nullptr;   // per-block scratch of the subset kernels
+    uint8_t* wscratch = nullptr;
     size_t wscratch_cap = 0;
-    QueryDesc* qd_host = nullptr;  // pinned
-    size_t qd_host_cap = 0;
-    hipEvent_t staged = nullptr;   // the last descriptor upload has completed
+    uint8_t* staging = nullptr;  // pinned: CallParams + QueryDesc[]
+    size_t staging_cap = 0;
+    hipEvent_t staged = nullptr; // the last upload has completed
     hipEvent_t ev[6] = {};
+    uint64_t generation = 0;     // bumped whenever a device buffer moves
+    // captured graph of the last batched call
+    std::string graph_key;
+    hipGraphExec_t graph_exec = nullptr;
 };
 
 struct DeviceCtx {
     uint64_t* binom = nullptr;
     int num_cu = 256;
     std::map<hipStream_t, Workspace*> ws;
+    std::map<std::string, Shape> tuned;   // (tier, p, K) -> shape
 };
 
 struct LastCall {
     Workspace* ws = nullptr;
     int nq = 0;
-    bool timing = false;
+    int timing = 0;   // 1: per stage, 2: whole call only
 };
 
 std::mutex g_mu;
@@ -106,6 +131,7 @@ td_status ensure_device(int dev, DeviceCtx** out) {
         for (int k = 0; k < td::kBinomK; ++k) tab[(size_t)n * td::kBinomK + k] = binom_host(n, k);
     if (hipMalloc(&c->binom, tab.size() * sizeof(uint64_t)) != hipSuccess) { delete c; return TD_ERR_OUT_OF_MEMORY; }
     if (hipMemcpy(c->binom, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(c->binom);
         delete c;
         return TD_ERR_HIP;
     }
@@ -115,12 +141,32 @@ td_status ensure_device(int dev, DeviceCtx** out) {
 }
 
 template <typename T>
-td_status grow(T** p, size_t* cap, size_t need) {
+td_status grow(Workspace* w, T** p, size_t* cap, size_t need) {
     if (*cap >= need && *p) return TD_OK;
     size_t nc = std::max(need, (size_t)(*cap * 3 / 2));
     if (*p) { hipFree(*p); *p = nullptr; }
-    if (hipMalloc(p, nc * sizeof(T)) != hipSuccess) { *cap = 0; return TD_ERR_OUT_OF_MEMORY; }
+    *cap = 0;
+    ++w->generation;
+    if (hipMalloc(p, nc * sizeof(T)) != hipSuccess) { *p = nullptr; return TD_ERR_OUT_OF_MEMORY; }
     *cap = nc;
+    return TD_OK;
+}
+
+td_status ensure_values(Workspace* w, size_t need) {
+    if (w->val_cap >= need && w->x64) return TD_OK;
+    size_t nc = std::max(need, w->val_cap * 3 / 2);
+    hipFree(w->x64);
+    hipFree(w->x32);
+    hipFree(w->xi);
+    w->x64 = nullptr;
+    w->x32 = nullptr;
+    w->xi = nullptr;
+    w->val_cap = 0;
+    ++w->generation;
+    if (hipMalloc(&w->x64, nc * sizeof(double)) != hipSuccess) return TD_ERR_OUT_OF_MEMORY;
+    if (hipMalloc(&w->x32, nc * sizeof(float)) != hipSuccess) return TD_ERR_OUT_OF_MEMORY;
+    if (hipMalloc(&w->xi, nc * 2 * sizeof(uint64_t)) != hipSuccess) return TD_ERR_OUT_OF_MEMORY;
+    w->val_cap = nc;
     return TD_OK;
 }
 
@@ -131,6 +177,7 @@ td_status get_workspace(DeviceCtx* dc, int dev, hipStream_t s, Workspace** out) 
     w->device = dev;
     w->stream = s;
     if (hipMalloc(&w->ctr, sizeof(Counters)) != hipSuccess) { delete w; return TD_ERR_OUT_OF_MEMORY; }
+    if (hipMalloc(&w->cp, sizeof(CallParams)) != hipSuccess) { hipFree(w->ctr); delete w; return TD_ERR_OUT_OF_MEMORY; }
     if (hipEventCreateWithFlags(&w->staged, hipEventDisableTiming) != hipSuccess) return TD_ERR_HIP;
     for (auto& e : w->ev)
         if (hipEventCreate(&e) != hipSuccess) return TD_ERR_HIP;
@@ -141,37 +188,22 @@ td_status get_workspace(DeviceCtx* dc, int dev, hipStream_t s, Workspace** out) 
 
 void free_workspace(Workspace* w) {
     if (!w) return;
+    if (w->graph_exec) hipGraphExecDestroy(w->graph_exec);
     hipFree(w->x64);
     hipFree(w->x32);
-    hipFree(w->nrm);
     hipFree(w->xi);
+    hipFree(w->nrm);
     hipFree(w->qd);
     hipFree(w->qs);
+    hipFree(w->cp);
     hipFree(w->deferred);
     hipFree(w->ctr);
     hipFree(w->wscratch);
-    if (w->qd_host) hipHostFree(w->qd_host);
+    if (w->staging) hipHostFree(w->staging);
     if (w->staged) hipEventDestroy(w->staged);
     for (auto& e : w->ev)
         if (e) hipEventDestroy(e);
     delete w;
-}
-
-td_status ensure_points(Workspace* w, size_t need) {
-    if (w->pts_cap >= need && w->x64) return TD_OK;
-    size_t nc = std::max(need, w->pts_cap * 3 / 2);
-    hipFree(w->x64);
-    hipFree(w->x32);
-    hipFree(w->xi);
-    w->x64 = nullptr;
-    w->x32 = nullptr;
-    w->xi = nullptr;
-    w->pts_cap = 0;
-    if (hipMalloc(&w->x64, nc * sizeof(double)) != hipSuccess) return TD_ERR_OUT_OF_MEMORY;
-    if (hipMalloc(&w->x32, nc * sizeof(float)) != hipSuccess) return TD_ERR_OUT_OF_MEMORY;
-    if (hipMalloc(&w->xi, nc * 2 * sizeof(uint64_t)) != hipSuccess) return TD_ERR_OUT_OF_MEMORY;
-    w->pts_cap = nc;
-    return TD_OK;
 }
 
 td_options defaults() {
@@ -179,12 +211,7 @@ td_options defaults() {
     std::memset(&o, 0, sizeof(o));
     o.precision = TD_PREC_FP32_FILTERED;
     o.autotune = 1;
-    o.chunk = 0;
-    o.grid_blocks = 0;
     o.filter_scale = 1.0;
-    o.force_exact = 0;
-    o.timing = 0;
-    o.deferred_capacity = 0;
     return o;
 }
 
@@ -197,15 +224,6 @@ td_status check_options(const td_options& o) {
     return TD_OK;
 }
 
-struct Problem {
-    const double* X;
-    int64_t n;
-    int32_t p;
-    const double* Z;
-    int64_t m;
-    int32_t* counts;
-};
-
 td_status check_problem(const Problem& pr) {
     if (pr.m < 0) return TD_ERR_INVALID_ARG;
     if (pr.m == 0) return TD_OK;
@@ -215,17 +233,184 @@ td_status check_problem(const Problem& pr) {
     return TD_OK;
 }
 
-// Shape of the launch for one (p, K) class.
-int class_K(int64_t n) { return std::max(64, next_pow2((int)n)) / 64; }
+// Tier of the subset kernels: the exact precision runs the filtered kernel
+// with every subset deferred to the exact tier.
+int subset_tier(const td_options& o) { return o.precision == TD_PREC_FP64_PLAIN ? 0 : 1; }
 
-int default_chunk(int p, int64_t n) {
-    (void)p;
-    (void)n;
-    return 256;
+std::string tune_key(int tier, int p, int K) {
+    return std::to_string(tier) + ":" + std::to_string(p) + ":" + std::to_string(K);
 }
 
-// The engine behind td_depth_ex (single class).
-td_status run_single(const Problem& pr, const td_options& o, hipStream_t stream) {
+struct ClassPlan {
+    int p = 0, K = 0, M = 0;
+    Shape shape;
+    int xblocks = 0;          // exact-tier grid
+    uint64_t items = 0;
+    uint64_t scratch_off = 0; // bytes
+    uint64_t scratch_per_block = 0;
+};
+
+struct Plan {
+    std::vector<QueryDesc> qd;
+    std::vector<ClassPlan> cls;
+    size_t values = 0, points = 0, scratch = 0;
+    int chunk = 256;
+    int prep_blocks = 1, fin_blocks = 1;
+};
+
+td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_options& o, Plan* plan) {
+    const int tier = subset_tier(o);
+    std::map<std::pair<int, int>, int> slot;
+    std::vector<int> qcls;
+    // one chunk for the whole call: the explicit option, else the tuned
+    // chunk of the first class, else 256
+    int chunk = o.chunk;
+    for (int i = 0; i < num; ++i) {
+        const Problem& pr = probs[i];
+        if (pr.m == 0) continue;
+        const int M = std::max(64, next_pow2((int)pr.n));
+        const int K = M / 64;
+        int ib = 0;
+        while ((1 << ib) < M) ++ib;
+        int c = -1;
+        if (pr.p >= 2) {
+            auto key = std::make_pair((int)pr.p, K);
+            auto it = slot.find(key);
+            if (it == slot.end()) {
+                if ((int)plan->cls.size() == td::kMaxClasses) return TD_ERR_UNSUPPORTED;
+                c = (int)plan->cls.size();
+                slot[key] = c;
+                ClassPlan cp;
+                cp.p = pr.p;
+                cp.K = K;
+                cp.M = M;
+                auto tt = dc->tuned.find(tune_key(tier, pr.p, K));
+                if (o.autotune && tt != dc->tuned.end()) {
+                    cp.shape = tt->second;
+                    if (chunk == 0) chunk = tt->second.chunk;
+                }
+                if (o.grid_blocks > 0) cp.shape.blocks = o.grid_blocks;
+                plan->cls.push_back(cp);
+            } else {
+                c = it->second;
+            }
+        }
+        for (int64_t q = 0; q < pr.m; ++q) {
+            QueryDesc d;
+            std::memset(&d, 0, sizeof(d));
+            d.X = pr.X;
+            d.z = pr.Z + (size_t)q * pr.p;
+            d.count = pr.counts + q;
+            d.n = (int)pr.n;
+            d.p = pr.p;
+            d.M = M;
+            d.idx_bits = ib;
+            d.cls = c;
+            plan->qd.push_back(d);
+            qcls.push_back(c);
+        }
+    }
+    if (chunk == 0) chunk = 256;
+    plan->chunk = chunk;
+    // group queries by class so that every class owns a contiguous item range
+    std::vector<int> order(plan->qd.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const int ca = qcls[a] < 0 ? 1 << 20 : qcls[a], cb = qcls[b] < 0 ? 1 << 20 : qcls[b];
+        return ca < cb;
+    });
+    std::vector<QueryDesc> sorted;
+    sorted.reserve(order.size());
+    for (int i : order) sorted.push_back(plan->qd[i]);
+    plan->qd.swap(sorted);
+    uint64_t item = 0;
+    size_t vals = 0, pts = 0;
+    for (size_t i = 0; i < plan->qd.size(); ++i) {
+        QueryDesc& d = plan->qd[i];
+        d.v_off = vals;
+        d.n_off = pts;
+        vals += (size_t)d.M * d.p;
+        pts += (size_t)d.M;
+        d.item_begin = item;
+        d.items = 0;
+        if (d.cls >= 0) {
+            const uint64_t nsub = binom_host(d.n, d.p - 2);
+            const uint64_t it = (nsub + chunk - 1) / chunk;
+            if (it > 0xffffffffull) return TD_ERR_UNSUPPORTED;
+            d.items = (uint32_t)it;
+            plan->cls[d.cls].items += it;
+            item += it;
+        }
+    }
+    plan->values = vals;
+    plan->points = pts;
+    uint64_t soff = 0;
+    for (ClassPlan& cp : plan->cls) {
+        int blocks = cp.shape.blocks > 0 ? cp.shape.blocks : dc->num_cu * 8;
+        if ((uint64_t)blocks > cp.items) blocks = (int)std::max<uint64_t>(1, cp.items);
+        cp.shape.blocks = blocks;
+        cp.xblocks = dc->num_cu * 4;
+        uint64_t per = std::max<uint64_t>(td::wave_scratch_bytes(cp.M), td_exact_scratch_bytes(cp.p));
+        per = (per + 255) & ~(uint64_t)255;
+        cp.scratch_per_block = per;
+        cp.scratch_off = soff;
+        soff += per * (uint64_t)std::max(blocks, cp.xblocks);
+    }
+    plan->scratch = std::max<uint64_t>(soff, 256);
+    const int nq = (int)plan->qd.size();
+    plan->prep_blocks = std::max(1, std::min(nq, dc->num_cu * 4));
+    plan->fin_blocks = std::max(1, std::min(1024, (nq + 255) / 256));
+    return TD_OK;
+}
+
+// Enqueues the kernels of a planned call on `s` (capturable: no memsets).
+td_status enqueue(const Plan& plan, const Pools& base, const td_options& o, hipStream_t s, Workspace* w,
+                  bool timing) {
+    if (timing) HIPCHK(hipEventRecord(w->ev[0], s));
+    HIPCHK(td_launch_init(&base, s));
+    HIPCHK(td_launch_prep(&base, plan.prep_blocks, s));
+    if (timing) HIPCHK(hipEventRecord(w->ev[1], s));
+    const int tier = subset_tier(o);
+    for (size_t c = 0; c < plan.cls.size(); ++c) {
+        const ClassPlan& cp = plan.cls[c];
+        if (cp.items == 0) continue;
+        Pools pl = base;
+        pl.cls = (int)c;
+        pl.wscratch_bytes = cp.scratch_per_block;
+        hipError_t e = tier == 0 ? td_launch_subset_plain(cp.p, cp.K, cp.shape.blocks, s, &pl)
+                                 : td_launch_subset_filt(cp.p, cp.K, cp.shape.blocks, s, &pl);
+        if (e != hipSuccess) return TD_ERR_HIP;
+    }
+    if (timing) HIPCHK(hipEventRecord(w->ev[2], s));
+    if (tier == 1) {
+        for (size_t c = 0; c < plan.cls.size(); ++c) {
+            const ClassPlan& cp = plan.cls[c];
+            if (cp.items == 0) continue;
+            Pools pl = base;
+            pl.cls = (int)c;
+            pl.wscratch_bytes = cp.scratch_per_block;
+            if (td_launch_exact(cp.p, cp.K, cp.xblocks, s, &pl, 0) != hipSuccess) return TD_ERR_HIP;
+        }
+    }
+    if (timing) HIPCHK(hipEventRecord(w->ev[3], s));
+    HIPCHK(td_launch_finalize(&base, plan.fin_blocks, s));
+    if (timing) HIPCHK(hipEventRecord(w->ev[4], s));
+    return TD_OK;
+}
+
+std::string graph_signature(const Plan& plan, const Pools& pl, const td_options& o, const Workspace* w) {
+    std::string k = std::to_string(subset_tier(o)) + "|" + std::to_string(w->generation) + "|" +
+                     std::to_string(plan.prep_blocks) + "|" + std::to_string(plan.fin_blocks) + "|" +
+                     std::to_string(pl.force_exact) + "|" + std::to_string(pl.filter_scale) + "|" +
+                     std::to_string(pl.chunk) + "|" + std::to_string(pl.defer_cap);
+    for (const ClassPlan& cp : plan.cls) {
+        k += "|" + std::to_string(cp.p) + "," + std::to_string(cp.K) + "," + std::to_string(cp.shape.blocks) + "," +
+             std::to_string(cp.scratch_per_block) + "," + std::to_string(cp.items > 0);
+    }
+    return k;
+}
+
+td_status run(const Problem* probs, int num, const td_options& o, hipStream_t stream, bool use_graph) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return TD_ERR_NO_DEVICE;
     DeviceCtx* dc = nullptr;
@@ -234,60 +419,67 @@ td_status run_single(const Problem& pr, const td_options& o, hipStream_t stream)
     Workspace* w = nullptr;
     st = get_workspace(dc, dev, stream, &w);
     if (st != TD_OK) return st;
+    Plan plan;
+    st = make_plan(dc, probs, num, o, &plan);
+    if (st != TD_OK) return st;
+    const int nq = (int)plan.qd.size();
+    if (nq == 0) return TD_OK;
 
-    const int p = pr.p;
-    const int n = (int)pr.n;
-    const int m = (int)pr.m;
-    const int M = std::max(64, next_pow2(n));
-    const int K = M / 64;
-    const int ks = p - 2;
-    const int chunk = o.chunk > 0 ? o.chunk : default_chunk(p, n);
-    const uint64_t nsub = (p >= 2) ? binom_host(n, ks) : 0;
-    const uint64_t ipq = (nsub + chunk - 1) / chunk;
-
-    // workspace sizes
-    if ((st = ensure_points(w, (size_t)m * M * p)) != TD_OK) return st;
-    if ((st = grow(&w->nrm, &w->nrm_cap, (size_t)m * M)) != TD_OK) return st;
-    size_t qcap = w->q_cap;
-    if ((st = grow(&w->qd, &qcap, (size_t)m)) != TD_OK) return st;
-    size_t qcap2 = w->q_cap;
-    if ((st = grow(&w->qs, &qcap2, (size_t)m)) != TD_OK) return st;
-    w->q_cap = std::min(qcap, qcap2);
+    // device memory
+    if ((st = ensure_values(w, std::max<size_t>(plan.values, 1))) != TD_OK) return st;
+    if ((st = grow(w, &w->nrm, &w->pts_cap, std::max<size_t>(plan.points, 1))) != TD_OK) return st;
+    if (w->q_cap < (size_t)nq || !w->qd || !w->qs) {
+        hipFree(w->qd);
+        hipFree(w->qs);
+        w->qd = nullptr;
+        w->qs = nullptr;
+        w->q_cap = 0;
+        ++w->generation;
+        const size_t nc = std::max((size_t)nq, w->q_cap * 3 / 2);
+        if (hipMalloc(&w->qd, nc * sizeof(QueryDesc)) != hipSuccess) return TD_ERR_OUT_OF_MEMORY;
+        if (hipMalloc(&w->qs, nc * sizeof(QueryState)) != hipSuccess) return TD_ERR_OUT_OF_MEMORY;
+        w->q_cap = nc;
+    }
     const int64_t dcap = o.deferred_capacity > 0 ? o.deferred_capacity : kDefaultDeferCap;
     if (w->defer_cap < dcap) {
         hipFree(w->deferred);
         w->deferred = nullptr;
-        if (hipMalloc(&w->deferred, (size_t)dcap * sizeof(Deferred)) != hipSuccess) { w->defer_cap = 0; return TD_ERR_OUT_OF_MEMORY; }
+        w->defer_cap = 0;
+        ++w->generation;
+        if (hipMalloc(&w->deferred, (size_t)dcap * sizeof(Deferred)) != hipSuccess) return TD_ERR_OUT_OF_MEMORY;
         w->defer_cap = dcap;
     }
-    // descriptors (pinned staging, reused once the previous upload is done)
+    if ((st = grow(w, &w->wscratch, &w->wscratch_cap, plan.scratch)) != TD_OK) return st;
+
+    // per-call data: pinned staging, reused once the previous upload is done
     HIPCHK(hipEventSynchronize(w->staged));
-    if (w->qd_host_cap < (size_t)m) {
-        if (w->qd_host) hipHostFree(w->qd_host);
-        w->qd_host = nullptr;
-        if (hipHostMalloc(&w->qd_host, (size_t)m * sizeof(QueryDesc)) != hipSuccess) return TD_ERR_OUT_OF_MEMORY;
-        w->qd_host_cap = m;
+    const size_t bytes = sizeof(CallParams) + (size_t)nq * sizeof(QueryDesc);
+    if (w->staging_cap < bytes) {
+        if (w->staging) hipHostFree(w->staging);
+        w->staging = nullptr;
+        w->staging_cap = 0;
+        if (hipHostMalloc(&w->staging, bytes) != hipSuccess) return TD_ERR_OUT_OF_MEMORY;
+        w->staging_cap = bytes;
     }
-    int ib = 0;
-    while ((1 << ib) < M) ++ib;
-    for (int q = 0; q < m; ++q) {
-        QueryDesc& d = w->qd_host[q];
-        d.X = pr.X;
-        d.z = pr.Z + (size_t)q * p;
-        d.count = pr.counts + q;
-        d.n = n;
-        d.p = p;
-        d.M = M;
-        d.idx_bits = ib;
-        d.x_off = (uint64_t)q * M;
-        d.item_begin = (uint64_t)q * ipq;
-        d.items = (uint32_t)ipq;
-        d.cls = 0;
+    CallParams* cph = reinterpret_cast<CallParams*>(w->staging);
+    std::memset(cph, 0, sizeof(CallParams));
+    cph->num_queries = nq;
+    cph->num_classes = (int)plan.cls.size();
+    uint64_t acc = 0;
+    for (size_t c = 0; c < plan.cls.size(); ++c) {
+        cph->cls_begin[c] = acc;
+        acc += plan.cls[c].items;
+        cph->cls_end[c] = acc;
+        cph->cls_scratch[c] = plan.cls[c].scratch_off;
     }
-    HIPCHK(hipMemcpyAsync(w->qd, w->qd_host, (size_t)m * sizeof(QueryDesc), hipMemcpyHostToDevice, stream));
+    std::memcpy(w->staging + sizeof(CallParams), plan.qd.data(), (size_t)nq * sizeof(QueryDesc));
+    HIPCHK(hipMemcpyAsync(w->cp, cph, sizeof(CallParams), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(w->qd, w->staging + sizeof(CallParams), (size_t)nq * sizeof(QueryDesc),
+                          hipMemcpyHostToDevice, stream));
     HIPCHK(hipEventRecord(w->staged, stream));
 
     Pools pl;
+    std::memset(&pl, 0, sizeof(pl));
     pl.x64 = w->x64;
     pl.x32 = w->x32;
     pl.nrm = w->nrm;
@@ -295,49 +487,71 @@ td_status run_single(const Problem& pr, const td_options& o, hipStream_t stream)
     pl.binom = dc->binom;
     pl.qs = w->qs;
     pl.qd = w->qd;
+    pl.cp = w->cp;
     pl.deferred = w->deferred;
     pl.ctr = w->ctr;
     pl.defer_cap = (uint64_t)dcap;
-    pl.total_items = ipq * (uint64_t)m;
-    pl.num_queries = m;
-    pl.chunk = chunk;
+    pl.chunk = plan.chunk;
     pl.filter_scale = std::isinf(o.filter_scale) ? 3.0e38f : (float)o.filter_scale;
-    pl.force_exact = o.force_exact;
-
-    int blocks = o.grid_blocks > 0 ? o.grid_blocks : dc->num_cu * 8;
-    if ((uint64_t)blocks > pl.total_items) blocks = (int)std::max<uint64_t>(1, pl.total_items);
-    const int xblocks = dc->num_cu * 4;   // exact-tier grid
-    uint64_t wsb = std::max<uint64_t>(td::wave_scratch_bytes(M), td_exact_scratch_bytes(p));
-    wsb = (wsb + 255) & ~(uint64_t)255;
-    if ((st = grow(&w->wscratch, &w->wscratch_cap, (size_t)std::max(blocks, xblocks) * wsb)) != TD_OK) return st;
+    pl.force_exact = (o.force_exact || o.precision == TD_PREC_EXACT) ? 1 : 0;
     pl.wscratch = w->wscratch;
-    pl.wscratch_bytes = wsb;
 
-    const bool timing = o.timing != 0;
-    if (timing) HIPCHK(hipEventRecord(w->ev[0], stream));
-    HIPCHK(td_launch_prep(&pl, std::min(m, dc->num_cu * 4), stream));
-    if (timing) HIPCHK(hipEventRecord(w->ev[1], stream));
-    if (p >= 2 && pl.total_items > 0) {
-        hipError_t e;
-        if (o.precision == TD_PREC_FP64_PLAIN) e = td_launch_subset_plain(p, K, blocks, stream, &pl);
-        else if (o.precision == TD_PREC_FP32_FILTERED) e = td_launch_subset_filt(p, K, blocks, stream, &pl);
-        else e = td_launch_exact(p, K, blocks, stream, &pl, 1);
-        if (e != hipSuccess) return TD_ERR_HIP;
-        if (timing) HIPCHK(hipEventRecord(w->ev[2], stream));
-        if (o.precision == TD_PREC_FP32_FILTERED) {
-            e = td_launch_exact(p, K, xblocks, stream, &pl, 0);
-            if (e != hipSuccess) return TD_ERR_HIP;
-        }
-    } else if (timing) {
-        HIPCHK(hipEventRecord(w->ev[2], stream));
-    }
-    if (timing) HIPCHK(hipEventRecord(w->ev[3], stream));
-    HIPCHK(td_launch_finalize(&pl, stream));
-    if (timing) HIPCHK(hipEventRecord(w->ev[4], stream));
     g_last.ws = w;
-    g_last.nq = m;
-    g_last.timing = timing;
+    g_last.nq = nq;
+    if (!use_graph) {
+        g_last.timing = o.timing ? 1 : 0;
+        return enqueue(plan, pl, o, stream, w, o.timing != 0);
+    }
+    // graph path: capture once per signature, replay afterwards
+    const std::string key = graph_signature(plan, pl, o, w);
+    if (key != w->graph_key || !w->graph_exec) {
+        if (w->graph_exec) {
+            hipGraphExecDestroy(w->graph_exec);
+            w->graph_exec = nullptr;
+        }
+        w->graph_key.clear();
+        hipStream_t cs = nullptr;
+        HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            hipStreamDestroy(cs);
+            return TD_ERR_HIP;
+        }
+        const td_status es = enqueue(plan, pl, o, cs, w, false);
+        const hipError_t ce = hipStreamEndCapture(cs, &g);
+        hipStreamDestroy(cs);
+        if (es != TD_OK || ce != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return es != TD_OK ? es : TD_ERR_HIP;
+        }
+        const hipError_t ie = hipGraphInstantiate(&w->graph_exec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            w->graph_exec = nullptr;
+            return TD_ERR_HIP;
+        }
+        w->graph_key = key;
+    }
+    g_last.timing = o.timing ? 2 : 0;
+    if (o.timing) HIPCHK(hipEventRecord(w->ev[0], stream));
+    HIPCHK(hipGraphLaunch(w->graph_exec, stream));
+    if (o.timing) HIPCHK(hipEventRecord(w->ev[4], stream));
     return TD_OK;
+}
+
+// Deterministic synthetic points for the autotuner: sums of four uniforms
+// from a 64-bit LCG, centred and scaled (plumbing only, no depth arithmetic).
+void synth(std::vector<double>& v, size_t count, uint64_t seed) {
+    v.resize(count);
+    uint64_t s = seed * 6364136223846793005ull + 1442695040888963407ull;
+    for (size_t i = 0; i < count; ++i) {
+        double acc = 0.0;
+        for (int k = 0; k < 4; ++k) {
+            s = s * 6364136223846793005ull + 1442695040888963407ull;
+            acc += (double)(s >> 11) * (1.0 / 9007199254740992.0);
+        }
+        v[i] = (acc - 2.0) * 1.7320508075688772;
+    }
 }
 
 }  // namespace
@@ -359,16 +573,37 @@ td_status td_depth_ex(const double* X, int64_t n, int32_t p, const double* Z, in
     st = check_problem(pr);
     if (st != TD_OK) return st;
     if (m == 0) return TD_OK;
-    if (o.precision == TD_PREC_EXACT) return TD_ERR_UNSUPPORTED;
     std::lock_guard<std::mutex> lk(g_mu);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return TD_ERR_NO_DEVICE;
-    return run_single(pr, o, (hipStream_t)stream);
+    return run(&pr, 1, o, (hipStream_t)stream, false);
 }
 
 td_status td_depth(const double* X, int64_t n, int32_t p, const double* Z, int64_t m, int32_t* counts,
                    void* stream) {
     return td_depth_ex(X, n, p, Z, m, counts, nullptr, stream);
+}
+
+td_status td_depth_batched(const td_problem* probs, int32_t num, const td_options* opt, void* stream) {
+    if (num < 0 || (num > 0 && !probs)) return TD_ERR_INVALID_ARG;
+    if (num == 0) return TD_OK;
+    td_options o = opt ? *opt : defaults();
+    td_status st = check_options(o);
+    if (st != TD_OK) return st;
+    std::vector<Problem> pv(num);
+    int64_t total = 0;
+    for (int i = 0; i < num; ++i) {
+        pv[i] = Problem{probs[i].X, probs[i].n, probs[i].p, probs[i].Z, probs[i].m, probs[i].counts};
+        st = check_problem(pv[i]);
+        if (st != TD_OK) return st;
+        total += pv[i].m;
+    }
+    if (total == 0) return TD_OK;
+    if (total > (int64_t)1 << 30) return TD_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_mu);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return TD_ERR_NO_DEVICE;
+    return run(pv.data(), num, o, (hipStream_t)stream, true);
 }
 
 td_status td_get_stats(td_stats* out) {
@@ -377,6 +612,7 @@ td_status td_get_stats(td_stats* out) {
     std::memset(out, 0, sizeof(*out));
     Workspace* w = g_last.ws;
     if (!w) return TD_OK;
+    HIPCHK(hipSetDevice(w->device));
     HIPCHK(hipDeviceSynchronize());
     Counters c;
     HIPCHK(hipMemcpy(&c, w->ctr, sizeof(c), hipMemcpyDeviceToHost));
@@ -387,14 +623,12 @@ td_status td_get_stats(td_stats* out) {
     out->degenerate_subsets = c.degenerate;
     out->invalid_subsets = c.invalid;
     std::vector<QueryState> qs(g_last.nq);
-    if (g_last.nq > 0) {
-        HIPCHK(hipMemcpy(qs.data(), w->qs, qs.size() * sizeof(QueryState), hipMemcpyDeviceToHost));
-    }
+    if (g_last.nq > 0) HIPCHK(hipMemcpy(qs.data(), w->qs, qs.size() * sizeof(QueryState), hipMemcpyDeviceToHost));
     int dst = 0;
     for (auto& s : qs) dst |= (s.status & 0xff);
     out->device_status = dst;
-    if (g_last.timing) {
-        float a = 0;
+    float a = 0;
+    if (g_last.timing == 1) {
         hipEventElapsedTime(&a, w->ev[0], w->ev[1]);
         out->prep_ms = a;
         hipEventElapsedTime(&a, w->ev[1], w->ev[2]);
@@ -403,10 +637,93 @@ td_status td_get_stats(td_stats* out) {
         out->exact_ms = a;
         hipEventElapsedTime(&a, w->ev[3], w->ev[4]);
         out->finalize_ms = a;
+    }
+    if (g_last.timing) {
         hipEventElapsedTime(&a, w->ev[0], w->ev[4]);
         out->total_ms = a;
     }
     return dst ? TD_ERR_DEVICE_STATUS : TD_OK;
+}
+
+td_status td_autotune(int32_t p, int64_t n, const td_options* base, void* stream) {
+    td_options o = base ? *base : defaults();
+    td_status st = check_options(o);
+    if (st != TD_OK) return st;
+    if (p < 2 || p > TD_MAX_P || n < 1 || n > TD_MAX_N) return TD_ERR_INVALID_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return TD_ERR_NO_DEVICE;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    hipStream_t s = (hipStream_t)stream;
+    // synthetic problem of the requested shape (4 queries)
+    const int m = 4;
+    std::vector<double> hx, hz;
+    synth(hx, (size_t)n * p, 1);
+    synth(hz, (size_t)m * p, 2);
+    double* dx = nullptr;
+    double* dz = nullptr;
+    int32_t* dcount = nullptr;
+    if (hipMalloc(&dx, hx.size() * sizeof(double)) != hipSuccess) return TD_ERR_OUT_OF_MEMORY;
+    if (hipMalloc(&dz, hz.size() * sizeof(double)) != hipSuccess) { hipFree(dx); return TD_ERR_OUT_OF_MEMORY; }
+    if (hipMalloc(&dcount, m * sizeof(int32_t)) != hipSuccess) {
+        hipFree(dx);
+        hipFree(dz);
+        return TD_ERR_OUT_OF_MEMORY;
+    }
+    td_status ret = TD_OK;
+    if (hipMemcpy(dx, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dz, hz.data(), hz.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        ret = TD_ERR_HIP;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    int num_cu = 256;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        DeviceCtx* dctx = nullptr;
+        if (ensure_device(dev, &dctx) == TD_OK) num_cu = dctx->num_cu;
+    }
+    const int K = std::max(64, next_pow2((int)n)) / 64;
+    const int tier = subset_tier(o);
+    float best = 1e30f;
+    Shape bs;
+    const int chunks[] = {64, 128, 256, 512};
+    const int grids[] = {2, 4, 8, 16};
+    for (int ci = 0; ci < 4 && ret == TD_OK; ++ci)
+        for (int gi = 0; gi < 4 && ret == TD_OK; ++gi) {
+            td_options t = o;
+            t.autotune = 0;
+            t.chunk = chunks[ci];
+            t.grid_blocks = num_cu * grids[gi];
+            t.timing = 0;
+            float ms = 0.0f;
+            for (int rep = 0; rep < 2; ++rep) {   // the first run warms up
+                hipEventRecord(e0, s);
+                const td_status r = td_depth_ex(dx, n, p, dz, m, dcount, &t, stream);
+                hipEventRecord(e1, s);
+                if (r != TD_OK) { ret = r; break; }
+                hipEventSynchronize(e1);
+                hipEventElapsedTime(&ms, e0, e1);
+            }
+            if (ret == TD_OK && ms < best) {
+                best = ms;
+                bs.chunk = t.chunk;
+                bs.blocks = t.grid_blocks;
+            }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(dx);
+    hipFree(dz);
+    hipFree(dcount);
+    if (ret != TD_OK) return ret;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceCtx* dctx = nullptr;
+    st = ensure_device(dev, &dctx);
+    if (st != TD_OK) return st;
+    dctx->tuned[tune_key(tier, p, K)] = bs;
+    return TD_OK;
 }
 
 const char* td_status_string(td_status s) {
@@ -436,21 +753,5 @@ void td_release(void) {
 }
 
 int32_t td_version(void) { return 1; }
-
-td_status td_depth_batched(const td_problem* probs, int32_t num, const td_options* opt, void* stream) {
-    if (num < 0 || (num > 0 && !probs)) return TD_ERR_INVALID_ARG;
-    if (num == 0) return TD_OK;
-    (void)opt;
-    (void)stream;
-    return TD_ERR_UNSUPPORTED;
-}
-
-td_status td_autotune(int32_t p, int64_t n, const td_options* base, void* stream) {
-    (void)p;
-    (void)n;
-    (void)base;
-    (void)stream;
-    return TD_ERR_UNSUPPORTED;
-}
 
 }  // extern "C"

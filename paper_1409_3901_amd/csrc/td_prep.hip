@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256) void prep_kernel(Pools pl) {
         __syncthreads();
         const int q = s_q;
         __syncthreads();
-        if (q >= pl.num_queries) break;
+        if (q >= pl.cp->num_queries) break;
         const QueryDesc d = pl.qd[q];
         const int n = d.n, p = d.p, M = d.M;
         if (tid < p) s_z[tid] = d.z[tid];
@@ -102,11 +102,10 @@ __global__ __launch_bounds__(256) void prep_kernel(Pools pl) {
         }
         __syncthreads();
         const int nnz = s_red[3];
-        const uint64_t off = d.x_off;
-        double* x64 = pl.x64 + off * p;
-        float* x32 = pl.x32 + off * p;
-        float* nrm = pl.nrm + off;
-        uint64_t* xi = pl.xi + off * p * 2;
+        double* x64 = pl.x64 + d.v_off;
+        float* x32 = pl.x32 + d.v_off;
+        float* nrm = pl.nrm + d.n_off;
+        uint64_t* xi = pl.xi + d.v_off * 2;
         const bool ints_ok = (emax - emin + 2) <= 125 && emin < (1 << 19);
         for (int i = tid; i < M; i += blockDim.x) {
             // padding rows beyond nnz are zero
@@ -179,7 +178,8 @@ __global__ __launch_bounds__(256) void prep_kernel(Pools pl) {
 
 // counts[q] = n0 + min over subsets, or -1 with a status bit.
 __global__ void finalize_kernel(Pools pl) {
-    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < pl.num_queries; q += gridDim.x * blockDim.x) {
+    const int nq = pl.cp->num_queries;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
         QueryState st = pl.qs[q];
         int bad = st.status & (kStNonfinite | kStDeferOverflow | kStExactRange | kStDegenLimit);
         int out;
@@ -198,16 +198,17 @@ __global__ void finalize_kernel(Pools pl) {
 
 }  // namespace td
 
-extern "C" hipError_t td_launch_prep(const td::Pools* pl, int blocks, hipStream_t s) {
+extern "C" hipError_t td_launch_init(const td::Pools* pl, hipStream_t s) {
     hipLaunchKernelGGL(td::init_kernel, dim3(1), dim3(64), 0, s, pl->ctr);
+    return hipGetLastError();
+}
+
+extern "C" hipError_t td_launch_prep(const td::Pools* pl, int blocks, hipStream_t s) {
     hipLaunchKernelGGL(td::prep_kernel, dim3(blocks), dim3(256), 0, s, *pl);
     return hipGetLastError();
 }
 
-extern "C" hipError_t td_launch_finalize(const td::Pools* pl, hipStream_t s) {
-    int blocks = (pl->num_queries + 255) / 256;
-    if (blocks < 1) blocks = 1;
-    if (blocks > 1024) blocks = 1024;
+extern "C" hipError_t td_launch_finalize(const td::Pools* pl, int blocks, hipStream_t s) {
     hipLaunchKernelGGL(td::finalize_kernel, dim3(blocks), dim3(256), 0, s, *pl);
     return hipGetLastError();
 }

@@ -442,7 +442,7 @@ __global__ __launch_bounds__(64) void subset_kernel(Pools pl) {
     __shared__ Slot slots[64];
     __shared__ uint16_t side[TIER == kPlain ? 1 : M];
     // per-block device scratch: float64 basis slots, then the staging arrays
-    uint8_t* wsc = pl.wscratch + (uint64_t)blockIdx.x * pl.wscratch_bytes;
+    uint8_t* wsc = pl.wscratch + pl.cp->cls_scratch[pl.cls] + (uint64_t)blockIdx.x * pl.wscratch_bytes;
     SlotF64<P>* slots64 = reinterpret_cast<SlotF64<P>*>(wsc);
     Staging sg;
     {
@@ -460,12 +460,15 @@ __global__ __launch_bounds__(64) void subset_kernel(Pools pl) {
     unsigned long long swept = 0, rechecks = 0, ndefer = 0, ninvalid = 0;
     FiltCtx fc;
     fc.fscale = pl.filter_scale;
+    const uint64_t cbeg = pl.cp->cls_begin[pl.cls];
+    const uint64_t cend = pl.cp->cls_end[pl.cls];
+    const int nq = pl.cp->num_queries;
     while (true) {
         unsigned long long item = 0;
-        if (lane == 0) item = atomicAdd(&pl.ctr->work_next, 1ull);
+        if (lane == 0) item = cbeg + atomicAdd(&pl.ctr->work_next[pl.cls], 1ull);
         item = uni64(__shfl(item, 0, 64));
-        if (item >= pl.total_items) break;
-        const int q = uni(item_query(pl.qd, pl.num_queries, item));
+        if (item >= cend) break;
+        const int q = uni(item_query(pl.qd, nq, item));
         const QueryDesc d = pl.qd[q];
         const QueryState st = pl.qs[q];
         if (st.status & kStNonfinite) continue;
@@ -474,9 +477,9 @@ __global__ __launch_bounds__(64) void subset_kernel(Pools pl) {
         const uint64_t r0 = uni64((item - d.item_begin) * (uint64_t)pl.chunk);
         const uint64_t r1 = uni64(min(r0 + (uint64_t)pl.chunk, nsub));
         if (r0 >= r1) continue;
-        const double* x64 = pl.x64 + d.x_off * P;
+        const double* x64 = pl.x64 + d.v_off;
         fc.x64 = x64;
-        fc.nrm = pl.nrm + d.x_off;
+        fc.nrm = pl.nrm + d.n_off;
         fc.idx_bits = d.idx_bits;
         int wbest = kBig;
         for (uint64_t rb = r0; rb < r1; rb += 64) {
@@ -531,8 +534,8 @@ __global__ __launch_bounds__(64) void subset_kernel(Pools pl) {
 #pragma unroll
                     for (int c = 0; c < P; ++c) xd[TIER == kPlain ? i : 0][c] = xb[(size_t)(lane * K + i) * P + c];
             } else {
-                const float* x32 = pl.x32 + d.x_off * P + opaque;
-                const float* nrm = pl.nrm + d.x_off + opaque;
+                const float* x32 = pl.x32 + d.v_off + opaque;
+                const float* nrm = pl.nrm + d.n_off + opaque;
 #pragma unroll
                 for (int i = 0; i < K; ++i) {
 #pragma unroll
