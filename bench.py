@@ -27,6 +27,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit lane-ops/s, non-packed: 39.3 T
+# Sources of the subset kernel: the HBM counters in the committed profile hold
+# only while these still hash to the fingerprint recorded there.
+KERNEL_SOURCES = ["td_subset.hpp", "td_device.hpp", "td_common.hpp",
+                  "td_subset_filt.hip", "td_subset_plain.hip"]
+PROFILE = os.path.join(ROOT, "profiles", "subset_kernel_c3_p5_n500.md")
+
+
+def kernel_fingerprint() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1409_3901_amd", "csrc", s), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the filtered subset kernel (FETCH_SIZE and
+    WRITE_SIZE, calibrated against a plain copy) from the committed profile,
+    or None when the kernel sources changed since the counters were taken."""
+    import re
+    try:
+        with open(PROFILE) as f:
+            txt = f.read()
+    except OSError:
+        return None
+    fp = re.search(r"kernel_sources_sha256: ([0-9a-f]{16})", txt)
+    tb = re.search(r"traffic_bytes_per_launch: ([0-9.e+]+)", txt)
+    if not fp or not tb or fp.group(1) != kernel_fingerprint():
+        return None
+    return float(tb.group(1))
 
 
 def algorithmic_ops(m: int, p: int) -> float:
@@ -46,6 +77,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (calibrates HBM counters)")
+    ap.add_argument("--precision", default="filtered", choices=["filtered", "plain"],
+                    help="tier timed as `value` (profiling runs)")
+    ap.add_argument("--c4", action="store_true",
+                    help="batched workload instead: 256 datasets in one graph launch vs "
+                         "256*8 plain float64 launches")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -70,6 +106,8 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes,
                           "dispatches": 3}), flush=True)
         return
+    if a.c4:
+        return bench_c4(a, td, workloads, torch, np, dev)
     X, Z = workloads.c3()
     n, p = X.shape
     m = Z.shape[0]
@@ -101,9 +139,10 @@ def main():
             sub_ms.append(st["subset_ms"])
         return total / a.steps, sum(sub_ms) / len(sub_ms), st, out.cpu().numpy()
 
-    ms, sub_ms, st, counts = timed("filtered")
+    ms, sub_ms, st, counts = timed(a.precision)
     res = {
-        "metric": "subset sweeps/s (float32-filtered, exact) at p=5, n=500",
+        "metric": "subset sweeps/s (%s) at p=5, n=500" % (
+            "float32-filtered, exact" if a.precision == "filtered" else "plain float64"),
         "value": sweeps / (ms / 1e3),
         "unit": "sweeps/s",
         "n_gpus": 1,
@@ -113,11 +152,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if a.precision == "filtered" else "f64",
         "data": "synthetic",
         "config": {"workload": "c3: p=5, n=500 multivariate t(3), m=32 queries "
                                "(16 sample points + 16 N(0,I_5)), all C(n',3) subsets",
-                   "p": p, "n": n, "m": m, "precision": "fp32-filtered+fp64+exact"},
+                   "p": p, "n": n, "m": m,
+                   "precision": "fp32-filtered+fp64+exact" if a.precision == "filtered" else "fp64-plain"},
         "queries_per_s": m / (ms / 1e3),
         "sweeps_per_step": sweeps,
         "fp64_rechecks_per_sweep": st["fp64_rechecks"] / max(1, st["subsets_swept"]),
@@ -135,10 +175,11 @@ def main():
     # roofline of the subset kernel: algorithmic ops over its event duration
     achieved = ops / (sub_ms / 1e3) / 1e12
     res["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS,
-                       "unit": "TOP/s", "frac": achieved / PEAK_VALU_TOPS, "traffic": None,
-                       "kernel": "subset_kernel<5,8,filtered>", "kernel_ms": sub_ms,
+                       "unit": "TOP/s", "frac": achieved / PEAK_VALU_TOPS,
+                       "traffic": profiled_traffic() if a.precision == "filtered" else None,
+                       "kernel": "subset_kernel<5,8,%s>" % a.precision, "kernel_ms": sub_ms,
                        "ops_per_launch": ops}
-    if not a.no_plain:
+    if not a.no_plain and a.precision == "filtered":
         pms, psub, pst, pcounts = timed("plain")
         res["plain_fp64"] = {"sweeps_per_s": sweeps / (pms / 1e3), "ms_per_step": pms,
                              "subset_kernel_ms": psub,
@@ -146,6 +187,54 @@ def main():
         res["speedup_filtered_vs_plain"] = pms / ms
     if not a.no_cpu:
         res["cpu_baseline"] = cpu_baseline(X, Z, a.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+def bench_c4(a, td, workloads, torch, np, dev):
+    """256 datasets of uneven n and p (8 queries each): one td_depth_batched
+    call (one captured graph launch) against one plain float64 td_depth call
+    per query."""
+    def note(msg):
+        print("[c4] %s" % msg, file=sys.stderr, flush=True)
+
+    data = workloads.c4()
+    note("generated %d datasets" % len(data))
+    probs = [(torch.from_numpy(X).to(dev), torch.from_numpy(Z).to(dev)) for X, Z in data]
+    sweeps = 0
+    for X, Z in data:
+        n, p = X.shape
+        for q in range(Z.shape[0]):
+            n0 = int(np.sum(np.all(X == Z[q], axis=1)))
+            sweeps += math.comb(n - n0, p - 2)
+    note("%d sweeps" % sweeps)
+    td.depth_batched(probs)       # captures the graph
+    torch.cuda.synchronize()
+    note("warm-up launch done")
+    t = time.time()
+    outs = td.depth_batched(probs)
+    torch.cuda.synchronize()
+    tb = time.time() - t
+    note("timed graph launch: %.2f s" % tb)
+    st = td.get_stats()
+    t = time.time()
+    plain = []
+    for i, (Xd, Zd) in enumerate(probs):
+        for q in range(Zd.shape[0]):
+            plain.append(td.depth(Xd, Zd[q:q + 1].contiguous(), precision="plain"))
+        if i % 32 == 31:
+            torch.cuda.synchronize()
+            note("plain launches: %d datasets, %.1f s" % (i + 1, time.time() - t))
+    torch.cuda.synchronize()
+    tp = time.time() - t
+    got = np.concatenate([o.cpu().numpy() for o in outs])
+    pl = np.concatenate([o.cpu().numpy() for o in plain])
+    res = {"metric": "c4 batched: sweeps/s of one graph launch (float32-filtered, exact)",
+           "value": sweeps / tb, "unit": "sweeps/s", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "c4: 256 datasets, p in {3,4,5}, n in [50,800], 8 queries each"},
+           "sweeps": sweeps, "batched_s": tb, "plain_launches": len(pl), "plain_s": tp,
+           "plain_sweeps_per_s": sweeps / tp, "speedup_batched_vs_plain_launches": tp / tb,
+           "mismatches_batched_vs_plain": int(np.sum(got != pl)),
+           "deferred_subsets": st["deferred_subsets"], "device_status": st["device_status"]}
     print(json.dumps(res), flush=True)
 
 
