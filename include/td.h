@@ -3,9 +3,9 @@
  *
  * The library computes depth counts  counts[q] = n * D_n(Z_q),  where
  *     D_n(z) = min over unit u of  #{ i : u'X_i <= u'z } / n
- * is the sample Tukey depth (Section 1, equation HDSV), with the paper's
+ * is the sample Tukey depth (Section 1, equation (1)), with the paper's
  * first algorithm (Section 3): the depth of the origin after the shift
- * x_i = X_i - z equals, by Proposition 1 with r = p-2 (equation HDSp22), the
+ * x_i = X_i - z equals, by Proposition 1 with r = p-2 (equation (8)), the
  * minimum over all (p-2)-subsets I of the observations of a bivariate depth,
  * obtained by projecting onto the 2-D complement of span(x_I) (Algorithm 1,
  * Step 1(a)-(b)) and running one angular sort and one circular sweep

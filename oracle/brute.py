@@ -3,17 +3,17 @@
 TEST INFRASTRUCTURE ONLY: used by tests to pin the C++ oracle; never by the
 product path.  Shares no code with the HIP path or with ``td_oracle.cpp``.
 
-* ``depth_vertex``  -- the critical-direction route (equation DNPp1, the
+* ``depth_vertex``  -- the critical-direction route (equation (4), the
   p-1 subset form of Proposition 1): the optimum of the closed-halfspace count
   is attained next to an extreme ray of an open cone of the central hyperplane
   arrangement {u : u'x_i = 0}; such a ray is normal to p-1 independent points;
   next to it the count is the strict count plus the depth, inside the
   hyperplane, of the points lying on it.  O(n^p), tiny inputs only.
-* ``depth_angular_p2`` -- p = 2 by brute force over the circle (definition
-  HDSV): every direction between two consecutive critical directions is
+* ``depth_angular_p2`` -- p = 2 by brute force over the circle (the definition,
+  equation (1)): every direction between two consecutive critical directions is
   generic; take the bisector of each consecutive pair and count.
 * ``depth_p1`` -- p = 1 closed form min(#{X <= z}, #{X >= z}) (Section 3).
-* ``upper_bound_directions`` -- HDSV evaluated at given directions: any
+* ``upper_bound_directions`` -- the definition (equation (1)) evaluated at given directions: any
   direction gives an upper bound.
 All inputs are floats; they are converted exactly with ``fractions.Fraction``
 and scaled to integers by the common denominator.
@@ -189,7 +189,7 @@ def depth_angular_p2(X, z):
 
 def upper_bound_directions(X, z, U):
     """min over the directions u in U of #{i : u'(X_i - z) <= 0}: an upper
-    bound of the depth count (definition HDSV)."""
+    bound of the depth count (the definition, equation (1))."""
     X = np.asarray(X, dtype=np.float64)
     z = np.asarray(z, dtype=np.float64).reshape(-1)
     D = X - z

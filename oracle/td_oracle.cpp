@@ -5,12 +5,12 @@
  * load this file; only tests, the smoke check and the CPU-baseline leg of the
  * benchmark use it.  It shares no code with the HIP path.
  *
- * What it computes (Section 1, sample depth, equation HDSV): for observations
+ * What it computes (Section 1, sample depth, equation (1)): for observations
  * X_1..X_n in R^p and a query z,
  *     d(z) = min over unit u of #{ i : u'(X_i - z) <= 0 },
  * the depth count (closed halfspaces).  The paper's first algorithm
  * (Section 3, Algorithm 1 with Algorithm 2 as its bivariate step, justified by
- * Proposition 1 with r = p-2, equation HDSp22) is followed step by step:
+ * Proposition 1 with r = p-2, equation (8)) is followed step by step:
  *
  *   shift to z = 0 (Section 2), drop the observations equal to z (they lie on
  *   every hyperplane and count n0 for every u);
@@ -355,7 +355,7 @@ PointSet restrict_rows(const PointSet& P, const std::vector<int>& idx, const std
 
 // ---------------------------------------------------- small exact depth
 // min over generic u of #{ v : u'v < 0 } for nonzero integer vectors, by the
-// critical-direction route (equation DNPp1): every optimal open cone has an
+// critical-direction route (equation (4)): every optimal open cone has an
 // extreme ray normal to d-1 independent points; near that ray the count is
 // the strict count plus the depth of the points on the hyperplane.
 int small_depth(const PointSet& V) {
@@ -754,7 +754,7 @@ int oracle_depth_range(const double* X, int64_t n, int32_t p, const double* z, u
     return 0;
 }
 
-// Depth count by the critical-direction route alone (equation DNPp1 with the
+// Depth count by the critical-direction route alone (equation (4) with the
 // exact recursion for points on the critical hyperplane).  O(n^p): tiny inputs.
 int oracle_depth_vertex(const double* X, int64_t n, int32_t p, const double* z, int64_t* out) {
     if (!X || !z || !out || n < 1 || p < 1) return 1;

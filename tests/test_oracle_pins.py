@@ -2,8 +2,8 @@
 
 Each pin is independent of the oracle's own code path:
   * p = 1 closed form min(#{X <= z}, #{X >= z}) (Section 3),
-  * p = 2 exhaustive search over the circle (definition HDSV),
-  * the critical-direction route (equation DNPp1) in exact Python integers
+  * p = 2 exhaustive search over the circle (the definition, equation (1)),
+  * the critical-direction route (equation (4)) in exact Python integers
     and in C++, on tiny inputs with heavy degeneracy (the paper validates its
     algorithms by agreement of independent methods, Section 5.1),
   * closed forms: exactly antipodal sets, queries outside the hull (vanishing
