@@ -6,8 +6,9 @@ N(0, I_5)); every query sweeps all C(n', 3) subsets (about 2.07e7).  One step
 = one td_depth call over the 32 queries with inputs already in HBM: the whole
 path (preparation, subset kernel, exact tier, finalisation).
 
-Prints ONE JSON line: subset sweeps/s of the float32-filtered path (`value`),
-queries/s, the plain float64 path's rate and the filtered/plain speedup, the
+Prints ONE JSON line: subset sweeps/s of the float32-filtered path with the
+bucketed sweep (`value`), queries/s, the rates of the filtered path with the
+full bitonic sort and of the plain float64 path with the speedups, the
 roofline object of the subset kernel (VALU-bound: algorithmic lane-ops per
 launch over its HIP-event duration) and the CPU oracle timed on a bounded
 sample of the same workload.
@@ -77,8 +78,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (calibrates HBM counters)")
-    ap.add_argument("--precision", default="filtered", choices=["filtered", "plain"],
-                    help="tier timed as `value` (profiling runs)")
+    ap.add_argument("--precision", default="filtered", choices=["filtered", "bitonic", "plain"],
+                    help="kernel timed as `value` (profiling runs): filtered = float32-filtered "
+                         "with the bucketed sweep, bitonic = float32-filtered with the full sort, "
+                         "plain = plain float64")
     ap.add_argument("--c4", action="store_true",
                     help="batched workload instead: 256 datasets in one graph launch vs "
                          "256*8 plain float64 launches")
@@ -118,9 +121,13 @@ def main():
     Zd = torch.from_numpy(Z).to(dev)
     stream = torch.cuda.current_stream()
 
+    OPTS = {"filtered": dict(precision="filtered"),
+            "bitonic": dict(precision="filtered", sweep="bitonic"),
+            "plain": dict(precision="plain")}
+
     def timed(prec):
         for _ in range(a.warmup):
-            td.depth(Xd, Zd, precision=prec, timing=True)
+            td.depth(Xd, Zd, timing=True, **OPTS[prec])
         torch.cuda.synchronize()
         sub_ms = []
         st = None
@@ -131,7 +138,7 @@ def main():
         for _ in range(a.steps):
             torch.cuda.synchronize()
             t0.record(stream)
-            out = td.depth(Xd, Zd, precision=prec, timing=True)
+            out = td.depth(Xd, Zd, timing=True, **OPTS[prec])
             t1.record(stream)
             torch.cuda.synchronize()
             total += t0.elapsed_time(t1)
@@ -140,9 +147,10 @@ def main():
         return total / a.steps, sum(sub_ms) / len(sub_ms), st, out.cpu().numpy()
 
     ms, sub_ms, st, counts = timed(a.precision)
+    names = {"filtered": "float32-filtered, exact, bucketed sweep",
+             "bitonic": "float32-filtered, exact, full bitonic sort", "plain": "plain float64"}
     res = {
-        "metric": "subset sweeps/s (%s) at p=5, n=500" % (
-            "float32-filtered, exact" if a.precision == "filtered" else "plain float64"),
+        "metric": "subset sweeps/s (%s) at p=5, n=500" % names[a.precision],
         "value": sweeps / (ms / 1e3),
         "unit": "sweeps/s",
         "n_gpus": 1,
@@ -152,12 +160,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if a.precision == "filtered" else "f64",
+        "dtype": "f64" if a.precision == "plain" else "f32",
         "data": "synthetic",
         "config": {"workload": "c3: p=5, n=500 multivariate t(3), m=32 queries "
                                "(16 sample points + 16 N(0,I_5)), all C(n',3) subsets",
                    "p": p, "n": n, "m": m,
-                   "precision": "fp32-filtered+fp64+exact" if a.precision == "filtered" else "fp64-plain"},
+                   "precision": "fp64-plain" if a.precision == "plain" else "fp32-filtered+fp64+exact",
+                   "sweep": "bitonic" if a.precision != "filtered" else "bucketed"},
         "queries_per_s": m / (ms / 1e3),
         "sweeps_per_step": sweeps,
         "fp64_rechecks_per_sweep": st["fp64_rechecks"] / max(1, st["subsets_swept"]),
@@ -177,9 +186,15 @@ def main():
     res["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS,
                        "unit": "TOP/s", "frac": achieved / PEAK_VALU_TOPS,
                        "traffic": profiled_traffic() if a.precision == "filtered" else None,
-                       "kernel": "subset_kernel<5,8,%s>" % a.precision, "kernel_ms": sub_ms,
+                       "kernel": "subset_kernel<5,8,%d>" % {"plain": 0, "bitonic": 1, "filtered": 3}[a.precision],
+                       "kernel_ms": sub_ms,
                        "ops_per_launch": ops}
     if not a.no_plain and a.precision == "filtered":
+        bms, bsub, bst, bcounts = timed("bitonic")
+        res["filtered_bitonic"] = {"sweeps_per_s": sweeps / (bms / 1e3), "ms_per_step": bms,
+                                   "subset_kernel_ms": bsub,
+                                   "mismatches_vs_bucketed": int(np.sum(bcounts != counts))}
+        res["speedup_bucketed_vs_bitonic"] = bms / ms
         pms, psub, pst, pcounts = timed("plain")
         res["plain_fp64"] = {"sweeps_per_s": sweeps / (pms / 1e3), "ms_per_step": pms,
                              "subset_kernel_ms": psub,

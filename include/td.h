@@ -76,6 +76,16 @@ typedef enum {
                                   exact fallback for every subset */
 } td_precision;
 
+/* Angular order of the filtered tier (Algorithm 2, Step 1(e)).  Both give the
+ * same exact counts. */
+typedef enum {
+    TD_SWEEP_AUTO = 0,    /* counting sort into pseudo-angle buckets, exact
+                             order only where the sweep minimum may lie (full
+                             sort when that region is large, or for 1024
+                             points in a sweep) */
+    TD_SWEEP_BITONIC = 1  /* full bitonic sort of every sweep */
+} td_sweep;
+
 typedef struct {
     int32_t precision;         /* td_precision (default TD_PREC_FP32_FILTERED) */
     int32_t autotune;          /* 1: use the tuned launch shape when cached */
@@ -88,6 +98,8 @@ typedef struct {
     int32_t force_exact;       /* 1: every subset goes through the exact tier */
     int32_t timing;            /* 1: record HIP events per stage (td_get_stats) */
     int64_t deferred_capacity; /* max deferred subsets per call, 0 = default */
+    int32_t sweep;             /* td_sweep: how the filtered tier orders the
+                                  projected points (default TD_SWEEP_AUTO) */
 } td_options;
 
 typedef struct {

@@ -23,6 +23,7 @@ TD_OK = 0
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported request", 3: "out of device memory",
           4: "HIP runtime error", 5: "some queries failed (see device_status)", 6: "no HIP device"}
 PRECISION = {"plain": 0, "fp64": 0, "filtered": 1, "fp32": 1, "exact": 2}
+SWEEP = {"auto": 0, "bucket": 0, "bitonic": 1}
 DEV_BITS = {1: "nonfinite", 2: "no_valid_subset", 4: "defer_overflow", 8: "exact_range",
             16: "degeneracy_limit"}
 MAX_P = 8
@@ -39,6 +40,7 @@ class Options(ctypes.Structure):
         ("force_exact", ctypes.c_int32),
         ("timing", ctypes.c_int32),
         ("deferred_capacity", ctypes.c_int64),
+        ("sweep", ctypes.c_int32),
     ]
 
 
@@ -117,7 +119,7 @@ def load():
 
 
 def options(precision="filtered", autotune=True, chunk=0, grid_blocks=0, filter_scale=1.0,
-            force_exact=False, timing=False, deferred_capacity=0) -> Options:
+            force_exact=False, timing=False, deferred_capacity=0, sweep="auto") -> Options:
     lib = load()
     o = Options()
     lib.td_default_options(ctypes.byref(o))
@@ -129,6 +131,7 @@ def options(precision="filtered", autotune=True, chunk=0, grid_blocks=0, filter_
     o.force_exact = 1 if force_exact else 0
     o.timing = 1 if timing else 0
     o.deferred_capacity = int(deferred_capacity)
+    o.sweep = SWEEP[sweep] if isinstance(sweep, str) else int(sweep)
     return o
 
 

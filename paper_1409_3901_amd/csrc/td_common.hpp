@@ -10,7 +10,8 @@ constexpr int kWave = 64;
 constexpr int kBinomK = 7;             // binomial table columns k = 0..6
 constexpr int kBinomN = kMaxN + 2;     // rows n = 0..kMaxN+1
 
-enum Tier : int { kPlain = 0, kFilt = 1, kExact = 2 };
+// kFiltBucket: the float32-filtered tier with the bucketed sweep.
+enum Tier : int { kPlain = 0, kFilt = 1, kExact = 2, kFiltBucket = 3 };
 
 // Query status bits (match TD_DEV_* of td.h).
 constexpr int kStNonfinite = 1;
@@ -95,6 +96,7 @@ struct Pools {
     float filter_scale;
     int32_t force_exact;
     int32_t cls;        // class slot of this launch (subset and exact kernels)
+    int32_t sweep_mode; // 0: bucketed sweep kernels, 1: full-sort kernels
     uint8_t* wscratch;       // per-block scratch in device memory
     uint64_t wscratch_bytes; // bytes per block
 };

@@ -72,6 +72,31 @@ __device__ __forceinline__ int wave_excl_max(int v, int id) {
     return lane == 0 ? id : prev;
 }
 
+// Inclusive prefix sum / min over the 64 lanes with DPP: row shifts 1, 2, 4, 8
+// inside each 16-lane row, then row broadcasts of lane 15 (to rows 1 and 3)
+// and lane 31 (to rows 2 and 3).  Lanes without a source read the identity.
+__device__ __forceinline__ int wave_incl_sum_dpp(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);
+    return v;
+}
+
+// Minimum over the 64 lanes (an inclusive min-scan read at lane 63), uniform.
+__device__ __forceinline__ int wave_min_dpp(int v) {
+    constexpr int I = 0x7fffffff;
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x111, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x112, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x114, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x118, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x142, 0xA, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x143, 0xC, 0xF, false));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
 // ------------------------------------------------------------ bitonic sort
 // Value of lane (lane ^ MASK) for the lane patterns of the bitonic network,
 // using DPP lane moves and the gfx950 permlane swaps where they exist:

@@ -25,6 +25,7 @@ extern "C" hipError_t td_launch_prep(const td::Pools* pl, int blocks, hipStream_
 extern "C" hipError_t td_launch_finalize(const td::Pools* pl, int blocks, hipStream_t s);
 extern "C" hipError_t td_launch_subset_plain(int P, int K, int blocks, hipStream_t s, const td::Pools* pl);
 extern "C" hipError_t td_launch_subset_filt(int P, int K, int blocks, hipStream_t s, const td::Pools* pl);
+extern "C" hipError_t td_launch_subset_bucket(int P, int K, int blocks, hipStream_t s, const td::Pools* pl);
 extern "C" hipError_t td_launch_exact(int P, int K, int blocks, hipStream_t s, const td::Pools* pl, int all_items);
 extern "C" uint64_t td_exact_scratch_bytes(int P);
 
@@ -221,6 +222,7 @@ td_status check_options(const td_options& o) {
     if (o.grid_blocks < 0) return TD_ERR_INVALID_ARG;
     if (!(o.filter_scale >= 0.0)) return TD_ERR_INVALID_ARG;   // rejects NaN
     if (o.deferred_capacity < 0) return TD_ERR_INVALID_ARG;
+    if (o.sweep < 0 || o.sweep > 1) return TD_ERR_INVALID_ARG;
     return TD_OK;
 }
 
@@ -233,9 +235,13 @@ td_status check_problem(const Problem& pr) {
     return TD_OK;
 }
 
-// Tier of the subset kernels: the exact precision runs the filtered kernel
-// with every subset deferred to the exact tier.
-int subset_tier(const td_options& o) { return o.precision == TD_PREC_FP64_PLAIN ? 0 : 1; }
+// Tier of the subset kernels: 0 plain float64, 1 filtered with the full sort,
+// 3 filtered with the bucketed sweep.  The exact precision runs a filtered
+// kernel with every subset deferred to the exact tier.
+int subset_tier(const td_options& o) {
+    if (o.precision == TD_PREC_FP64_PLAIN) return 0;
+    return o.sweep == TD_SWEEP_BITONIC ? 1 : 3;
+}
 
 std::string tune_key(int tier, int p, int K) {
     return std::to_string(tier) + ":" + std::to_string(p) + ":" + std::to_string(K);
@@ -377,12 +383,13 @@ td_status enqueue(const Plan& plan, const Pools& base, const td_options& o, hipS
         Pools pl = base;
         pl.cls = (int)c;
         pl.wscratch_bytes = cp.scratch_per_block;
-        hipError_t e = tier == 0 ? td_launch_subset_plain(cp.p, cp.K, cp.shape.blocks, s, &pl)
-                                 : td_launch_subset_filt(cp.p, cp.K, cp.shape.blocks, s, &pl);
+        hipError_t e = tier == 0   ? td_launch_subset_plain(cp.p, cp.K, cp.shape.blocks, s, &pl)
+                       : tier == 1 ? td_launch_subset_filt(cp.p, cp.K, cp.shape.blocks, s, &pl)
+                                   : td_launch_subset_bucket(cp.p, cp.K, cp.shape.blocks, s, &pl);
         if (e != hipSuccess) return TD_ERR_HIP;
     }
     if (timing) HIPCHK(hipEventRecord(w->ev[2], s));
-    if (tier == 1) {
+    if (tier != 0) {
         for (size_t c = 0; c < plan.cls.size(); ++c) {
             const ClassPlan& cp = plan.cls[c];
             if (cp.items == 0) continue;
@@ -402,7 +409,8 @@ std::string graph_signature(const Plan& plan, const Pools& pl, const td_options&
     std::string k = std::to_string(subset_tier(o)) + "|" + std::to_string(w->generation) + "|" +
                      std::to_string(plan.prep_blocks) + "|" + std::to_string(plan.fin_blocks) + "|" +
                      std::to_string(pl.force_exact) + "|" + std::to_string(pl.filter_scale) + "|" +
-                     std::to_string(pl.chunk) + "|" + std::to_string(pl.defer_cap);
+                     std::to_string(pl.chunk) + "|" + std::to_string(pl.defer_cap) + "|" +
+                     std::to_string(pl.sweep_mode);
     for (const ClassPlan& cp : plan.cls) {
         k += "|" + std::to_string(cp.p) + "," + std::to_string(cp.K) + "," + std::to_string(cp.shape.blocks) + "," +
              std::to_string(cp.scratch_per_block) + "," + std::to_string(cp.items > 0);
@@ -494,6 +502,7 @@ td_status run(const Problem* probs, int num, const td_options& o, hipStream_t st
     pl.chunk = plan.chunk;
     pl.filter_scale = std::isinf(o.filter_scale) ? 3.0e38f : (float)o.filter_scale;
     pl.force_exact = (o.force_exact || o.precision == TD_PREC_EXACT) ? 1 : 0;
+    pl.sweep_mode = o.sweep;
     pl.wscratch = w->wscratch;
 
     g_last.ws = w;

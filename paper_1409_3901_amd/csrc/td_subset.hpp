@@ -18,6 +18,7 @@ namespace td {
 
 constexpr int kDefer = -2;
 constexpr int kSkip = -3;
+constexpr int kFallback = -4;   // bucketed sweep gave up: use the full sort
 constexpr int kBig = 0x7fffffff;
 
 template <int P>
@@ -414,6 +415,346 @@ __device__ int sweep_filt(const float (&xr)[K][P], const float (&nr)[K], const S
     return wave_min(best);
 }
 
+// ---------------------------------------------------------------- bucketed
+// The sweep only needs the states where min(S, m - S) can be smallest, so the
+// angular order is taken at bucket granularity first (a counting sort by
+// pseudo-angle) and refined exactly only where the minimum may lie.
+//
+// Keys: t' in [0, 2] maps to q = t' QS + W - QS ... in quanta, q in
+// [W, (NB - 1) W], with NB = M buckets of W = 2^31 / NB quanta.  Every point
+// carries a certified interval [q - rq, q + rq] (rq < W / 4) that contains the
+// key of the exact frame, so a bucket boundary that no interval crosses is a
+// strict gap of the angular order, and the state there is a state of the
+// sweep.  Bucket word (LDS): bits 0-10 points folded with delta = -1, bits
+// 11-21 points with delta = +1 (counted by the bucket of the interval's lower
+// end), bits 22-31 points whose interval crosses into the next bucket.
+//
+// With S_j the state at the left boundary of bucket j (by counts), the states
+// reachable inside the bucket lie in [S_j - pos_j - c_j, S_j + neg_j + c_j],
+// c_j the points crossing in from bucket j-1.  U = min of min(S, m - S) over
+// boundaries that no interval crosses (real states), L = min over buckets of
+// the range bound; L <= b_I <= U.  When L = U the sweep is done; otherwise the
+// runs of buckets (between uncrossed boundaries) whose range dips below U are
+// gathered and walked in exact order from the state at their left boundary.
+constexpr uint32_t kHistPos = 1u;
+constexpr uint32_t kHistNeg = 1u << 11;
+constexpr uint32_t kHistStr = 1u << 22;
+constexpr uint32_t kAuxNeg = 1u << 31;
+constexpr int kListMax = 128;   // gathered points of the runs walked exactly
+
+template <int K>
+struct BucketGeom {
+    static constexpr int NB = 64 * K;
+    static constexpr int LOGNB = 6 + (K >= 2) + (K >= 4) + (K >= 8) + (K >= 16);
+    static constexpr int SH = 31 - LOGNB;
+    static constexpr uint32_t W = 1u << SH;
+    static constexpr double QS = (double)(NB - 2) * (double)W / 2.0;   // quanta per unit of t'
+    static constexpr uint32_t RQMAX = W / 4;
+};
+
+// float64 key of a point in bucket quanta; false if not certified
+template <int K>
+__device__ __forceinline__ bool bucket_key64(double d1, double d2, double eps64, uint32_t& q, uint32_t& aux) {
+    using G = BucketGeom<K>;
+    double t, r;
+    bool pos;
+    if (!key64(d1, d2, eps64, pos, t, r)) return false;
+    const double rqd = r * G::QS;
+    if (!(rqd < (double)(G::RQMAX - 4))) return false;
+    // t' = t in [0, 2]: q = (t - 1) QS + QS + W
+    q = (uint32_t)(t * G::QS + (double)G::W);
+    aux = ((uint32_t)rqd + 2u) | (pos ? 0u : kAuxNeg);
+    return true;
+}
+
+template <int P, int K>
+__device__ int sweep_bucket(const float (&xr)[K][P], const float (&nr)[K], const SlotFilt<P>& S,
+                            const SlotF64<P>& S64, int nnz, const FiltCtx& fc, uint32_t* hist, uint4* list,
+                            const Staging& sg, unsigned long long& rechecks) {
+    using G = BucketGeom<K>;
+    constexpr int KS = P - 2;
+    constexpr int NB = G::NB;
+    const int lane = lane_id();
+    const float QSf = (float)G::QS;
+    const float QBf = (float)(G::QS + (double)G::W);
+    float f1[P], f2[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        f1[c] = unif(S.f1[c]);
+        f2[c] = unif(S.f2[c]);
+    }
+    int mem[KS > 0 ? KS : 1];
+#pragma unroll
+    for (int c = 0; c < KS; ++c) mem[c] = uni(S.mem[c]);
+    const float beta = unif(S.beta32 * fc.fscale);
+    uint32_t qk[K], aux[K];
+    uint32_t weak = 0, vmask = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int idx = lane * K + i;
+        bool valid = idx < nnz;
+#pragma unroll
+        for (int c = 0; c < KS; ++c) valid = valid && (idx != mem[c]);
+        float y1 = 0.0f, y2 = 0.0f;
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+            y1 = fmaf(f1[c], xr[i][c], y1);
+            y2 = fmaf(f2[c], xr[i][c], y2);
+        }
+        // Fold by the sign of the first coordinate, pseudo-angle
+        // t' = h2 / (h1 + |h2|) + 1.  With eps the float32 error of each
+        // coordinate and a = eps / s <= 1/4 (from h1 > 4 eps), the key moves by
+        // at most eps / (s - 2 eps) = a / (1 - 2a) <= a + 4a^2; 8 u32 covers
+        // the rounding of t' (hardware reciprocal within 1 ulp) and of the
+        // scaling to quanta (Algorithm 2, Step 1(b)).
+        const float eps = beta * nr[i];
+        const bool pos = y1 > 0.0f;
+        const float ay1 = fabsf(y1);
+        const float h2 = pos ? y2 : -y2;
+        const float s = ay1 + fabsf(h2);
+        const float rs = __builtin_amdgcn_rcpf(s);
+        const float u = h2 * rs;
+        const float a = eps * rs;
+        const float r = fmaf(4.0f * a, a, a);
+        const float rqf = fmaf(r, QSf * 1.001f, 8.0f * kU32 * QSf);
+        const bool ok = (ay1 > 4.0f * eps) && (rqf < (float)(G::RQMAX - 4));
+        qk[i] = (uint32_t)fmaf(u, QSf, QBf);
+        aux[i] = ((uint32_t)rqf + 2u) | (pos ? 0u : kAuxNeg);
+        weak |= (valid && !ok) ? (1u << i) : 0u;
+        vmask |= valid ? (1u << i) : 0u;
+    }
+    if (__any(weak != 0)) {
+        // float32 cannot settle the fold or the key: float64 re-check through
+        // the staging arrays (rolled loop, rare path)
+        uint32_t* wq = sg.pkey + lane * K;
+        int* wa = sg.pS + lane * K;
+        int defer = 0;
+#pragma unroll 1
+        for (int i = 0; i < K; ++i) {
+            if (!((weak >> i) & 1u)) continue;
+            const int idx = lane * K + i;
+            ++rechecks;
+            double d1, d2;
+            fp64_point<P>(fc.x64, S64.e1, S64.e2, idx, d1, d2);
+            uint32_t q2, a2;
+            if (bucket_key64<K>(d1, d2, S64.beta64 * (double)fc.nrm[idx], q2, a2)) {
+                wq[i] = q2;
+                wa[i] = (int)a2;
+            } else {
+                defer = 1;
+            }
+        }
+        if (__any(defer)) return kDefer;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if ((weak >> i) & 1u) {
+                qk[i] = wq[i];
+                aux[i] = (uint32_t)wa[i];
+            }
+    }
+    // histogram
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const uint32_t rq = aux[i] & 0x7fffffffu;
+        const uint32_t blo = (qk[i] - rq) >> G::SH;
+        const bool str = ((qk[i] + rq) >> G::SH) != blo;
+        const uint32_t inc = ((aux[i] & kAuxNeg) ? kHistNeg : kHistPos) + (str ? kHistStr : 0u);
+        if ((vmask >> i) & 1u) atomicAdd(&hist[blo & (NB - 1)], inc);
+    }
+    __syncthreads();
+    // scan of the lane's K buckets [lane K, lane K + K)
+    uint32_t w[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) w[j] = hist[lane * K + j];
+#pragma unroll
+    for (int j = 0; j < K; ++j) hist[lane * K + j] = 0u;
+    uint32_t tl = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) tl += w[j];
+    tl &= 0x3fffffu;   // per-field sums stay below 2^11: no carry between fields
+    const int pre = wave_excl_sum((int)tl);
+    const int tot = __shfl((int)tl + pre, 63, 64);
+    const int S0 = uni(tot & 0x7ff);
+    const int m = uni(S0 + ((tot >> 11) & 0x7ff));
+    const int Sst = S0 - (pre & 0x7ff) + ((pre >> 11) & 0x7ff);
+    int cin = __shfl_up((int)(w[K - 1] >> 22), 1, 64);
+    if (lane == 0) cin = 0;
+    int U = kBig, L = kBig;
+    {
+        int s = Sst;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int np = (int)(w[j] & 0x7ffu);
+            const int nn = (int)((w[j] >> 11) & 0x7ffu);
+            const int c = (j == 0) ? cin : (int)(w[j - 1] >> 22);
+            if (c == 0) U = min(U, fside(s, m));
+            L = min(L, min(s - np - c, m - (s + nn + c)));
+            s += nn - np;
+        }
+    }
+    U = wave_min(U);
+    L = wave_min(L);
+    if (L >= U) return U;
+
+    // ---- rare: walk the runs whose range dips below U in exact order.
+    // Run info per bucket: (first bucket of its run << 11) | state at the
+    // run's left boundary; bit 31 of a run's first entry marks it for the walk.
+    int loc[K];
+    uint32_t hot = 0;
+    int last = -1;
+    {
+        int s = Sst;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int np = (int)(w[j] & 0x7ffu);
+            const int nn = (int)((w[j] >> 11) & 0x7ffu);
+            const int c = (j == 0) ? cin : (int)(w[j - 1] >> 22);
+            if (c == 0) last = ((lane * K + j) << 11) | s;
+            loc[j] = last;
+            if (min(s - np - c, m - (s + nn + c)) < U) hot |= 1u << j;
+            s += nn - np;
+        }
+    }
+    {
+        const int carry = wave_excl_max(last, -1);   // bucket 0 starts a run: carry >= 0 where needed
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (loc[j] < 0) loc[j] = carry;
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) hist[lane * K + j] = (uint32_t)loc[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if ((hot >> j) & 1u) atomicOr(&hist[(loc[j] >> 11) & (NB - 1)], 0x80000000u);
+    __syncthreads();
+    uint32_t gm = 0;
+    int cnt = 0;
+    uint32_t rinf[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const uint32_t rq = aux[i] & 0x7fffffffu;
+        const uint32_t blo = ((qk[i] - rq) >> G::SH) & (NB - 1);
+        const uint32_t ri = hist[blo] & 0x7fffffffu;
+        rinf[i] = ri;
+        const bool g = ((vmask >> i) & 1u) && (hist[(ri >> 11) & (NB - 1)] >> 31);
+        gm |= g ? (1u << i) : 0u;
+        cnt += g ? 1 : 0;
+    }
+    const int gbase = wave_excl_sum(cnt);
+    const int gtot = uni(__shfl(gbase + cnt, 63, 64));
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < K; ++j) hist[lane * K + j] = 0u;
+    if (gtot > kListMax) {
+        __syncthreads();
+        return kFallback;   // too many points to walk: the caller runs the full sort
+    }
+    {
+        int k = gbase;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if ((gm >> i) & 1u) {
+                list[k] = make_uint4(qk[i], aux[i], rinf[i], (uint32_t)(lane * K + i));
+                ++k;
+            }
+    }
+    __syncthreads();
+    int best = kBig, defer = 0;
+    if (lane == 0) {
+        // insertion sort by key (runs are separated by strict gaps, so the
+        // key order keeps every run contiguous and in order)
+#pragma unroll 1
+        for (int a = 1; a < gtot; ++a) {
+            const uint4 v = list[a];
+            int b = a;
+            while (b > 0 && list[b - 1].x > v.x) {
+                list[b] = list[b - 1];
+                --b;
+            }
+            list[b] = v;
+        }
+        int k = 0;
+#pragma unroll 1
+        while (k < gtot && !defer) {
+            const uint32_t run = list[k].z >> 11;
+            int s = (int)(list[k].z & 0x7ffu);
+            int a = k;
+#pragma unroll 1
+            while (a < gtot && (list[a].z >> 11) == run && !defer) {
+                // cluster: maximal run of overlapping intervals
+                const uint4 va = list[a];
+                uint32_t mhi = va.x + (va.y & 0x7fffffffu);
+                int hp = (va.y & kAuxNeg) ? 0 : 1, hn = 1 - hp;
+                int b = a;
+                while (b + 1 < gtot && (list[b + 1].z >> 11) == run &&
+                       list[b + 1].x - (list[b + 1].y & 0x7fffffffu) <= mhi) {
+                    ++b;
+                    const uint4 vb = list[b];
+                    mhi = max(mhi, vb.x + (vb.y & 0x7fffffffu));
+                    hp |= (vb.y & kAuxNeg) ? 0 : 1;
+                    hn |= (vb.y & kAuxNeg) ? 1 : 0;
+                }
+                const int c = b - a + 1;
+                if (hp && hn) {
+                    // both fold signs inside uncertain order: float64 keys,
+                    // insertion-sorted in the block's staging arrays
+                    if (c > kClusterMax) { defer = 1; break; }
+                    double* rt = sg.rt;
+                    float* rr = sg.rr;
+                    bool ok = true;
+#pragma unroll 1
+                    for (int u = 0; u < c; ++u) {
+                        const int idx = (int)list[a + u].w;
+                        double d1, d2, t, r;
+                        bool pos;
+                        fp64_point<P>(fc.x64, S64.e1, S64.e2, idx, d1, d2);
+                        const double eps64 = S64.beta64 * (double)fc.nrm[idx];
+                        if (!key64(d1, d2, eps64, pos, t, r)) { ok = false; break; }
+                        const float rf = (float)(r * 1.0000001) + 1e-30f;   // rounded up
+                        int v = u;
+                        while (v > 0 && rt[v - 1] > t) {
+                            rt[v] = rt[v - 1];
+                            rr[v] = rr[v - 1];
+                            --v;
+                        }
+                        rt[v] = t;
+                        rr[v] = pos ? rf : -rf;
+                    }
+                    rechecks += (unsigned long long)c;
+                    if (!ok) { defer = 1; break; }
+                    double thi = rt[0] + (double)fabsf(rr[0]);
+                    int sp = rr[0] < 0.0f, sn = rr[0] > 0.0f;
+                    s += (rr[0] < 0.0f) ? 1 : -1;
+#pragma unroll 1
+                    for (int u = 1; u < c; ++u) {
+                        const double tu = rt[u];
+                        const float ru = rr[u];
+                        if (tu - (double)fabsf(ru) > thi) {
+                            if (sp && sn) { ok = false; break; }
+                            best = min(best, fside(s, m));
+                            sp = sn = 0;
+                        }
+                        sp |= ru < 0.0f;
+                        sn |= ru > 0.0f;
+                        thi = fmax(thi, tu + (double)fabsf(ru));
+                        s += (ru < 0.0f) ? 1 : -1;
+                    }
+                    if (!ok || (sp && sn)) { defer = 1; break; }
+                } else {
+                    s += hn ? c : -c;
+                }
+                best = min(best, fside(s, m));
+                a = b + 1;
+            }
+            k = a;
+        }
+    }
+    __syncthreads();
+    if (__shfl(defer, 0, 64)) return kDefer;
+    return min(U, __shfl(best, 0, 64));
+}
+
 // ------------------------------------------------------------------ kernel
 template <int P, int TIER>
 struct SlotOf { using type = SlotFilt<P>; };
@@ -440,7 +781,10 @@ __global__ __launch_bounds__(64) void subset_kernel(Pools pl) {
     constexpr int M = 64 * K;
     using Slot = typename SlotOf<P, TIER>::type;
     __shared__ Slot slots[64];
-    __shared__ uint16_t side[TIER == kPlain ? 1 : M];
+    constexpr bool BUCKET = TIER == kFiltBucket;
+    __shared__ uint16_t side[TIER == kFilt ? M : 1];
+    __shared__ uint32_t hist[BUCKET ? M : 1];
+    __shared__ uint4 glist[BUCKET ? kListMax : 1];
     // per-block device scratch: float64 basis slots, then the staging arrays
     uint8_t* wsc = pl.wscratch + pl.cp->cls_scratch[pl.cls] + (uint64_t)blockIdx.x * pl.wscratch_bytes;
     SlotF64<P>* slots64 = reinterpret_cast<SlotF64<P>*>(wsc);
@@ -454,6 +798,11 @@ __global__ __launch_bounds__(64) void subset_kernel(Pools pl) {
         sg.pflag = p0 + (size_t)M * 20;
     }
     const int lane = lane_id();
+    if constexpr (BUCKET) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) hist[lane * K + j] = 0u;
+        __syncthreads();
+    }
     double xd[TIER == kPlain ? K : 1][P];
     float xf[TIER == kPlain ? 1 : K][P];
     float nr[TIER == kPlain ? 1 : K];
@@ -555,8 +904,19 @@ __global__ __launch_bounds__(64) void subset_kernel(Pools pl) {
                     if (sstate == 3) {
                         term = kDefer;
                     } else {
-                        term = sweep_filt<P, K>(xf, nr, reinterpret_cast<const SlotFilt<P>&>(S), slots64[s], nnz, fc,
-                                                side, sg, rechecks);
+                        if constexpr (BUCKET) {
+                            // bucket words count at most 1023 points per field;
+                            // what the bucketed sweep cannot finish goes to the
+                            // exact tier
+                            term = kDefer;
+                            if (nnz - KS <= 1023)
+                                term = sweep_bucket<P, K>(xf, nr, reinterpret_cast<const SlotFilt<P>&>(S), slots64[s],
+                                                          nnz, fc, hist, glist, sg, rechecks);
+                            if (term == kFallback) term = kDefer;
+                        } else {
+                            term = sweep_filt<P, K>(xf, nr, reinterpret_cast<const SlotFilt<P>&>(S), slots64[s], nnz,
+                                                    fc, side, sg, rechecks);
+                        }
                     }
                 }
                 if (term == kDefer) {

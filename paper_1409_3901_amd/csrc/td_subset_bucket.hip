@@ -1,0 +1,39 @@
+// Instantiations of the subset kernel: float32-filtered tier, bucketed sweep.
+#include "td_subset.hpp"
+
+namespace {
+using namespace td;
+typedef void (*KernelFn)(Pools);
+
+template <int P>
+KernelFn pick_k(int K) {
+    switch (K) {
+        case 1: return subset_kernel<P, 1, kFiltBucket>;
+        case 2: return subset_kernel<P, 2, kFiltBucket>;
+        case 4: return subset_kernel<P, 4, kFiltBucket>;
+        case 8: return subset_kernel<P, 8, kFiltBucket>;
+        case 16: return subset_kernel<P, 16, kFiltBucket>;
+    }
+    return nullptr;
+}
+
+KernelFn pick(int P, int K) {
+    switch (P) {
+        case 2: return pick_k<2>(K);
+        case 3: return pick_k<3>(K);
+        case 4: return pick_k<4>(K);
+        case 5: return pick_k<5>(K);
+        case 6: return pick_k<6>(K);
+        case 7: return pick_k<7>(K);
+        case 8: return pick_k<8>(K);
+    }
+    return nullptr;
+}
+}  // namespace
+
+extern "C" hipError_t td_launch_subset_bucket(int P, int K, int blocks, hipStream_t s, const td::Pools* pl) {
+    KernelFn f = pick(P, K);
+    if (!f) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(f, dim3(blocks), dim3(64), 0, s, *pl);
+    return hipGetLastError();
+}

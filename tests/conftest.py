@@ -30,6 +30,16 @@ def dev():
     return torch.device("cuda:0")
 
 
+# Options of the three kernels the parity tests cover: the plain float64
+# tier, the float32-filtered tier with the bucketed sweep (the default) and
+# the filtered tier with the full bitonic sort.
+PREC_OPTS = {
+    "plain": dict(precision="plain"),
+    "filtered": dict(precision="filtered"),
+    "bitonic": dict(precision="filtered", sweep="bitonic"),
+}
+
+
 def to_dev(a, dev):
     import numpy as np
     import torch

@@ -35,7 +35,7 @@ def test_struct_layouts_match_header():
     """The binding's ctypes structures have the sizes of the C structures."""
     import paper_1409_3901_amd as td
     # sizeof(td_options), sizeof(td_problem), sizeof(td_stats) on x86-64
-    assert ctypes.sizeof(td.Options) == 40
+    assert ctypes.sizeof(td.Options) == 48
     assert ctypes.sizeof(td.Problem) == 48
     assert ctypes.sizeof(td.Stats) == 72
 

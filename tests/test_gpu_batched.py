@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workloads
-from conftest import to_dev
+from conftest import PREC_OPTS, to_dev
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -54,11 +54,11 @@ def test_batched_graph_replay_and_equal_to_single(td, dev):
             assert np.array_equal(o.cpu().numpy(), single.cpu().numpy())
 
 
-@pytest.mark.parametrize("prec", ["plain", "filtered"])
+@pytest.mark.parametrize("prec", ["plain", "filtered", "bitonic"])
 def test_batched_precisions(td, dev, prec):
     probs = _small_batch(41, num=10)
     probs = [(X, Z) for X, Z in probs if X.shape[0] > 12]   # general position only
-    outs = td.depth_batched([(to_dev(X, dev), to_dev(Z, dev)) for X, Z in probs], precision=prec)
+    outs = td.depth_batched([(to_dev(X, dev), to_dev(Z, dev)) for X, Z in probs], **PREC_OPTS[prec])
     for (X, Z), o in zip(probs, outs):
         assert np.array_equal(o.cpu().numpy(), oracle.depth_counts(X, Z))
 
@@ -74,9 +74,9 @@ def test_launch_shapes_do_not_change_counts(td, dev):
     ref2 = oracle.depth_counts(X2, Z2)
     for chunk in (64, 128, 512):
         for grid in (17, 256, 2048):
-            for prec in ("plain", "filtered"):
-                a = td.depth(to_dev(X, dev), to_dev(Z, dev), precision=prec, chunk=chunk, grid_blocks=grid)
-                b = td.depth(to_dev(X2, dev), to_dev(Z2, dev), precision=prec, chunk=chunk, grid_blocks=grid)
+            for prec in ("plain", "filtered", "bitonic"):
+                a = td.depth(to_dev(X, dev), to_dev(Z, dev), chunk=chunk, grid_blocks=grid, **PREC_OPTS[prec])
+                b = td.depth(to_dev(X2, dev), to_dev(Z2, dev), chunk=chunk, grid_blocks=grid, **PREC_OPTS[prec])
                 assert np.array_equal(a.cpu().numpy(), ref1)
                 assert np.array_equal(b.cpu().numpy(), ref2)
 
