@@ -31,7 +31,7 @@ PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit lane-ops/s, non-packed: 39.3
 # Sources of the subset kernel: the HBM counters in the committed profile hold
 # only while these still hash to the fingerprint recorded there.
 KERNEL_SOURCES = ["td_subset.hpp", "td_device.hpp", "td_common.hpp",
-                  "td_subset_filt.hip", "td_subset_plain.hip"]
+                  "td_subset_bucket.hip", "td_subset_filt.hip", "td_subset_plain.hip"]
 PROFILE = os.path.join(ROOT, "profiles", "subset_kernel_c3_p5_n500.md")
 
 

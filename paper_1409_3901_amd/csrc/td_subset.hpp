@@ -552,14 +552,16 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const float (&nr)[K], const
                 aux[i] = (uint32_t)wa[i];
             }
     }
-    // histogram
+    // histogram, branch-free: points that are not swept add 0 to a word of
+    // their own lane past the buckets (hist holds NB + 64 words)
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const uint32_t rq = aux[i] & 0x7fffffffu;
         const uint32_t blo = (qk[i] - rq) >> G::SH;
         const bool str = ((qk[i] + rq) >> G::SH) != blo;
         const uint32_t inc = ((aux[i] & kAuxNeg) ? kHistNeg : kHistPos) + (str ? kHistStr : 0u);
-        if ((vmask >> i) & 1u) atomicAdd(&hist[blo & (NB - 1)], inc);
+        const bool v = (vmask >> i) & 1u;
+        atomicAdd(&hist[v ? (blo & (NB - 1)) : (uint32_t)(NB + lane)], v ? inc : 0u);
     }
     __syncthreads();
     // scan of the lane's K buckets [lane K, lane K + K)
@@ -572,13 +574,15 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const float (&nr)[K], const
 #pragma unroll
     for (int j = 0; j < K; ++j) tl += w[j];
     tl &= 0x3fffffu;   // per-field sums stay below 2^11: no carry between fields
-    const int pre = wave_excl_sum((int)tl);
-    const int tot = __shfl((int)tl + pre, 63, 64);
-    const int S0 = uni(tot & 0x7ff);
-    const int m = uni(S0 + ((tot >> 11) & 0x7ff));
+    const int incl = wave_incl_sum_dpp((int)tl);
+    const int pre = incl - (int)tl;
+    const int tot = __builtin_amdgcn_readlane(incl, 63);
+    const int S0 = tot & 0x7ff;
+    const int m = S0 + ((tot >> 11) & 0x7ff);
     const int Sst = S0 - (pre & 0x7ff) + ((pre >> 11) & 0x7ff);
-    int cin = __shfl_up((int)(w[K - 1] >> 22), 1, 64);
-    if (lane == 0) cin = 0;
+    // crossings into this lane's first bucket: the previous lane's last
+    // bucket (DPP wave_shr:1; lane 0 reads 0)
+    const int cin = __builtin_amdgcn_update_dpp(0, (int)(w[K - 1] >> 22), 0x138, 0xF, 0xF, false);
     int U = kBig, L = kBig;
     {
         int s = Sst;
@@ -592,8 +596,8 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const float (&nr)[K], const
             s += nn - np;
         }
     }
-    U = wave_min(U);
-    L = wave_min(L);
+    U = wave_min_dpp(U);
+    L = wave_min_dpp(L);
     if (L >= U) return U;
 
     // ---- rare: walk the runs whose range dips below U in exact order.
@@ -641,8 +645,9 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const float (&nr)[K], const
         gm |= g ? (1u << i) : 0u;
         cnt += g ? 1 : 0;
     }
-    const int gbase = wave_excl_sum(cnt);
-    const int gtot = uni(__shfl(gbase + cnt, 63, 64));
+    const int gincl = wave_incl_sum_dpp(cnt);
+    const int gbase = gincl - cnt;
+    const int gtot = __builtin_amdgcn_readlane(gincl, 63);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < K; ++j) hist[lane * K + j] = 0u;
@@ -751,8 +756,8 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const float (&nr)[K], const
         }
     }
     __syncthreads();
-    if (__shfl(defer, 0, 64)) return kDefer;
-    return min(U, __shfl(best, 0, 64));
+    if (__builtin_amdgcn_readfirstlane(defer)) return kDefer;
+    return min(U, __builtin_amdgcn_readfirstlane(best));
 }
 
 // ------------------------------------------------------------------ kernel
@@ -783,7 +788,7 @@ __global__ __launch_bounds__(64) void subset_kernel(Pools pl) {
     __shared__ Slot slots[64];
     constexpr bool BUCKET = TIER == kFiltBucket;
     __shared__ uint16_t side[TIER == kFilt ? M : 1];
-    __shared__ uint32_t hist[BUCKET ? M : 1];
+    __shared__ uint32_t hist[BUCKET ? M + 64 : 1];
     __shared__ uint4 glist[BUCKET ? kListMax : 1];
     // per-block device scratch: float64 basis slots, then the staging arrays
     uint8_t* wsc = pl.wscratch + pl.cp->cls_scratch[pl.cls] + (uint64_t)blockIdx.x * pl.wscratch_bytes;
@@ -801,6 +806,7 @@ __global__ __launch_bounds__(64) void subset_kernel(Pools pl) {
     if constexpr (BUCKET) {
 #pragma unroll
         for (int j = 0; j < K; ++j) hist[lane * K + j] = 0u;
+        hist[M + lane] = 0u;
         __syncthreads();
     }
     double xd[TIER == kPlain ? K : 1][P];
