@@ -29,52 +29,10 @@ __device__ __forceinline__ T shfl_xor_t(T v, int mask) {
     return __shfl_xor(v, mask, 64);
 }
 
-__device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-// exclusive prefix sum over the 64 lanes
-__device__ __forceinline__ int wave_excl_sum(int v) {
-    const int lane = lane_id();
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    return x - v;
-}
-
-// exclusive prefix max over the 64 lanes (identity `id` for lane 0)
-__device__ __forceinline__ int wave_excl_max(int v, int id) {
-    const int lane = lane_id();
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int y = __shfl_up(x, o, 64);
-        if (lane >= o) x = max(x, y);
-    }
-    int prev = __shfl_up(x, 1, 64);
-    return lane == 0 ? id : prev;
-}
-
-// Inclusive prefix sum / min over the 64 lanes with DPP: row shifts 1, 2, 4, 8
-// inside each 16-lane row, then row broadcasts of lane 15 (to rows 1 and 3)
-// and lane 31 (to rows 2 and 3).  Lanes without a source read the identity.
+// Wave-wide scans with DPP: row shifts 1, 2, 4, 8 inside each 16-lane row,
+// then row broadcasts of lane 15 (to rows 1 and 3) and lane 31 (to rows 2
+// and 3).  Lanes without a source read the identity.  Every helper below
+// expects the whole wave to be active.
 __device__ __forceinline__ int wave_incl_sum_dpp(int v) {
     v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);
     v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);
@@ -85,8 +43,7 @@ __device__ __forceinline__ int wave_incl_sum_dpp(int v) {
     return v;
 }
 
-// Minimum over the 64 lanes (an inclusive min-scan read at lane 63), uniform.
-__device__ __forceinline__ int wave_min_dpp(int v) {
+__device__ __forceinline__ int wave_incl_min_dpp(int v) {
     constexpr int I = 0x7fffffff;
     v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x111, 0xF, 0xF, false));
     v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x112, 0xF, 0xF, false));
@@ -94,7 +51,43 @@ __device__ __forceinline__ int wave_min_dpp(int v) {
     v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x118, 0xF, 0xF, false));
     v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x142, 0xA, 0xF, false));
     v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x143, 0xC, 0xF, false));
-    return __builtin_amdgcn_readlane(v, 63);
+    return v;
+}
+
+__device__ __forceinline__ int wave_incl_max_dpp(int v) {
+    constexpr int I = (int)0x80000000;
+    v = max(v, __builtin_amdgcn_update_dpp(I, v, 0x111, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(I, v, 0x112, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(I, v, 0x114, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(I, v, 0x118, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(I, v, 0x142, 0xA, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(I, v, 0x143, 0xC, 0xF, false));
+    return v;
+}
+
+// Totals (uniform: read from lane 63).
+__device__ __forceinline__ int wave_sum(int v) { return __builtin_amdgcn_readlane(wave_incl_sum_dpp(v), 63); }
+__device__ __forceinline__ int wave_min(int v) { return __builtin_amdgcn_readlane(wave_incl_min_dpp(v), 63); }
+__device__ __forceinline__ int wave_max(int v) { return __builtin_amdgcn_readlane(wave_incl_max_dpp(v), 63); }
+__device__ __forceinline__ int wave_min_dpp(int v) { return wave_min(v); }
+
+// exclusive prefix sum over the 64 lanes
+__device__ __forceinline__ int wave_excl_sum(int v) { return wave_incl_sum_dpp(v) - v; }
+
+// exclusive prefix max over the 64 lanes (identity `id` for lane 0): the
+// inclusive scan moved up one lane (DPP wave_shr:1)
+__device__ __forceinline__ int wave_excl_max(int v, int id) {
+    return __builtin_amdgcn_update_dpp(id, wave_incl_max_dpp(v), 0x138, 0xF, 0xF, false);
+}
+
+
+// Value of the previous lane (DPP wave_shr:1; lane 0 reads `id`) and of the
+// next lane (wave_shl:1; lane 63 reads `id`).
+__device__ __forceinline__ int lane_prev(int v, int id) {
+    return __builtin_amdgcn_update_dpp(id, v, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int lane_next(int v, int id) {
+    return __builtin_amdgcn_update_dpp(id, v, 0x130, 0xF, 0xF, false);
 }
 
 // ------------------------------------------------------------ bitonic sort

@@ -120,7 +120,8 @@ __device__ int sweep_plain(const double (&xr)[K][P], const SlotPlain<P>& S, int 
         loc += dl[i];
     }
     int s = S0 + wave_excl_sum(loc);
-    const uint64_t nxt = __shfl_down(key[0], 1, 64);
+    const uint64_t nxt = ((uint64_t)(uint32_t)lane_next((int)(key[0] >> 32), 0) << 32) |
+                         (uint32_t)lane_next((int)(uint32_t)key[0], 0);
     int best = (lane == 0) ? fside(S0, m) : kBig;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
@@ -304,7 +305,7 @@ __device__ int sweep_filt(const float (&xr)[K][P], const float (&nr)[K], const S
     {
         const uint32_t sdl = side[key[K - 1] & imask];
         const int dl_last_lane = (key[K - 1] != 0xffffffffu) ? ((sdl & kSideNeg) ? 1 : -1) : 0;
-        dl_before = __shfl_up(dl_last_lane, 1, 64);
+        dl_before = lane_prev(dl_last_lane, 0);
     }
     int dp = dl_before;
 #pragma unroll
@@ -329,8 +330,8 @@ __device__ int sweep_filt(const float (&xr)[K][P], const float (&nr)[K], const S
     }
     {
         // last element of the lane: look at the next lane's first element
-        const int nstart = __shfl_down((int)(startm & 1u), 1, 64);
-        const int nreal = __shfl_down((int)(key[0] != 0xffffffffu), 1, 64);
+        const int nstart = lane_next((int)(startm & 1u), 0);
+        const int nreal = lane_next((int)(key[0] != 0xffffffffu), 0);
         const bool ends = (lane == 63) || nstart || !nreal;
         if (prev_real && ends) best = min(best, fside(prev_s, m));
     }
@@ -582,7 +583,7 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const float (&nr)[K], const
     const int Sst = S0 - (pre & 0x7ff) + ((pre >> 11) & 0x7ff);
     // crossings into this lane's first bucket: the previous lane's last
     // bucket (DPP wave_shr:1; lane 0 reads 0)
-    const int cin = __builtin_amdgcn_update_dpp(0, (int)(w[K - 1] >> 22), 0x138, 0xF, 0xF, false);
+    const int cin = lane_prev((int)(w[K - 1] >> 22), 0);
     int U = kBig, L = kBig;
     {
         int s = Sst;
