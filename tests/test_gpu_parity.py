@@ -144,3 +144,29 @@ def test_c5_lattice_stress(td, dev, prec):
     print("c5", prec, "checked", len(qs), "mismatches", mism, st)
     if prec != "plain":
         assert mism == 0, (got.tolist(), exp.tolist())
+
+
+def test_p1_closed_form(td, dev):
+    """p = 1 has no subsets: the count is n0 + min(#{x > 0}, #{x < 0}), i.e.
+    min(#{X <= z}, #{X >= z}) (Section 3, the trivial case)."""
+    from oracle import brute
+    rng = np.random.default_rng(23)
+    for n in (1, 2, 7, 50, 1024):
+        X = rng.integers(-5, 6, size=(n, 1)).astype(np.float64)
+        Z = np.vstack([X[:3], rng.integers(-7, 8, size=(5, 1)).astype(np.float64)])
+        got = run(td, dev, X, Z)
+        exp = np.array([brute.depth_p1(X, z) for z in Z])
+        assert np.array_equal(got, exp), (n, got, exp)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("p,n", [(2, 150), (3, 120), (4, 60), (5, 40)])
+def test_every_sample_point(td, dev, prec, p, n):
+    """The depth of every observation (Z = X: m = n queries, each with
+    n0 >= 1), the workload of the paper's per-observation experiments."""
+    rng = np.random.default_rng(1000 + 10 * p + n)
+    X = rng.standard_normal((n, p))
+    got = run(td, dev, X, X, **PREC_OPTS[prec])
+    exp = oracle.depth_counts(X, X)
+    assert np.array_equal(got, exp), (int(np.sum(got != exp)),)
+    assert np.all(got >= 1)
