@@ -19,7 +19,7 @@ __global__ void init_kernel(Counters* ctr) {
 // lie on every hyperplane through z and add n0 to every count), and store
 // the nonzero points compacted in input order:
 //   x64 : float64 centred values (one rounding),
-//   x32 : float32 copies,
+//   x32 : float32 copies scaled to unit length,
 //   nrm : float32 upper bound of ||x||_2 of the float64 values,
 //   xi  : exact integers (X - z) * 2^-E, E the lowest bit exponent over the
 //         query's inputs (two's complement, 128 bits).
@@ -123,12 +123,22 @@ __global__ __launch_bounds__(256) void prep_kernel(Pools pl) {
             if (!s_flag[i]) continue;
             const int j = s_pos[i];
             double ss = 0.0;
+#pragma unroll
+            for (int c = 0; c < kMaxP; ++c)
+                if (c < p) {
+                    const double v = d.X[(size_t)i * p + c] - s_z[c];
+                    ss = fma(v, v, ss);
+                }
+            // float32 copy scaled to unit length: the float32 filter only
+            // needs directions (the pseudo-angle and the fold of a point do
+            // not change under positive scaling), and unit length makes its
+            // error radius the same for every point
+            const double inv = 1.0 / sqrt(ss);
             for (int c = 0; c < p; ++c) {
                 const double xv = d.X[(size_t)i * p + c];
                 const double v = xv - s_z[c];
                 x64[(size_t)j * p + c] = v;
-                x32[(size_t)j * p + c] = (float)v;
-                ss = fma(v, v, ss);
+                x32[(size_t)j * p + c] = (float)(v * inv);
                 uint64_t lo = 0, hi = 0;
                 if (ints_ok) {
                     uint64_t alo, ahi, blo, bhi;

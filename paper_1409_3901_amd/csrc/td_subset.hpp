@@ -31,7 +31,7 @@ struct SlotPlain {
 template <int P>
 struct SlotFilt {        // LDS: what every sweep reads
     float f1[P], f2[P];
-    float beta32;    // float32 projection error <= beta32 * ||x||_2
+    float beta32;    // float32 projection error of a unit-length point
     int32_t state;   // 0 ok, 1 skip (out of range / invalid), 3 defer
     int16_t mem[P > 2 ? P - 2 : 1];
 };
@@ -177,7 +177,7 @@ __device__ __forceinline__ bool key64(double y1, double y2, double eps, bool& po
 }
 
 template <int P, int K>
-__device__ int sweep_filt(const float (&xr)[K][P], const float (&nr)[K], const SlotFilt<P>& S,
+__device__ int sweep_filt(const float (&xr)[K][P], const SlotFilt<P>& S,
                           const SlotF64<P>& S64, int nnz, const FiltCtx& fc, uint16_t* side, const Staging& sg,
                           unsigned long long& rechecks) {
     uint32_t* pkey = sg.pkey;
@@ -226,7 +226,7 @@ __device__ int sweep_filt(const float (&xr)[K][P], const float (&nr)[K], const S
         // float32 error eps of each coordinate the key error is at most
         // eps / (s - 2 eps) plus the rounding of t' (Algorithm 2, Step 1(b)).
         // Branch-free: invalid and uncertain points are masked afterwards.
-        const float eps = beta * nr[i];
+        const float eps = beta;
         const bool pos = y1 > 0.0f;
         const float h1 = fabsf(y1);
         const float h2 = pos ? y2 : -y2;
@@ -469,7 +469,7 @@ __device__ __forceinline__ bool bucket_key64(double d1, double d2, double eps64,
 }
 
 template <int P, int K>
-__device__ int sweep_bucket(const float (&xr)[K][P], const float (&nr)[K], const SlotFilt<P>& S,
+__device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
                             const SlotF64<P>& S64, int nnz, const FiltCtx& fc, uint32_t* hist, uint4* list,
                             const Staging& sg, unsigned long long& rechecks) {
     using G = BucketGeom<K>;
@@ -487,7 +487,8 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const float (&nr)[K], const
     int mem[KS > 0 ? KS : 1];
 #pragma unroll
     for (int c = 0; c < KS; ++c) mem[c] = uni(S.mem[c]);
-    const float beta = unif(S.beta32 * fc.fscale);
+    // 4 eps, eps the float32 error of each coordinate of a unit-length point
+    const float eps4 = unif(4.0f * S.beta32 * fc.fscale);
     uint32_t qk[K], aux[K];
     uint32_t weak = 0, vmask = 0;
 #pragma unroll
@@ -505,22 +506,21 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const float (&nr)[K], const
         // Fold by the sign of the first coordinate, pseudo-angle
         // t' = h2 / (h1 + |h2|) + 1.  With eps the float32 error of each
         // coordinate and a = eps / s <= 1/4 (from h1 > 4 eps), the key moves by
-        // at most eps / (s - 2 eps) = a / (1 - 2a) <= a + 4a^2; 8 u32 covers
-        // the rounding of t' (hardware reciprocal within 1 ulp) and of the
-        // scaling to quanta (Algorithm 2, Step 1(b)).
-        const float eps = beta * nr[i];
+        // at most eps / (s - 2 eps) = a / (1 - 2a) <= a + 4a^2 = (b + b^2) / 4
+        // with b = 4a; 8 u32 covers the rounding of t' (hardware reciprocal
+        // within 1 ulp) and of the scaling to quanta, 2 quanta the truncations
+        // (Algorithm 2, Step 1(b)).
         const bool pos = y1 > 0.0f;
         const float ay1 = fabsf(y1);
         const float h2 = pos ? y2 : -y2;
         const float s = ay1 + fabsf(h2);
         const float rs = __builtin_amdgcn_rcpf(s);
         const float u = h2 * rs;
-        const float a = eps * rs;
-        const float r = fmaf(4.0f * a, a, a);
-        const float rqf = fmaf(r, QSf * 1.001f, 8.0f * kU32 * QSf);
-        const bool ok = (ay1 > 4.0f * eps) && (rqf < (float)(G::RQMAX - 4));
+        const float b = eps4 * rs;
+        const float rqf = fmaf(fmaf(b, b, b), QSf * (1.001f / 4.0f), 8.0f * kU32 * QSf + 2.0f);
+        const bool ok = (ay1 > eps4) && (rqf < (float)(G::RQMAX - 4));
         qk[i] = (uint32_t)fmaf(u, QSf, QBf);
-        aux[i] = ((uint32_t)rqf + 2u) | (pos ? 0u : kAuxNeg);
+        aux[i] = (uint32_t)rqf | (pos ? 0u : kAuxNeg);
         weak |= (valid && !ok) ? (1u << i) : 0u;
         vmask |= valid ? (1u << i) : 0u;
     }
@@ -559,8 +559,8 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const float (&nr)[K], const
     for (int i = 0; i < K; ++i) {
         const uint32_t rq = aux[i] & 0x7fffffffu;
         const uint32_t blo = (qk[i] - rq) >> G::SH;
-        const bool str = ((qk[i] + rq) >> G::SH) != blo;
-        const uint32_t inc = ((aux[i] & kAuxNeg) ? kHistNeg : kHistPos) + (str ? kHistStr : 0u);
+        // crossing count field: 1 when the interval ends in the next bucket
+        const uint32_t inc = ((aux[i] & kAuxNeg) ? kHistNeg : kHistPos) | ((((qk[i] + rq) >> G::SH) - blo) << 22);
         const bool v = (vmask >> i) & 1u;
         atomicAdd(&hist[v ? (blo & (NB - 1)) : (uint32_t)(NB + lane)], v ? inc : 0u);
     }
@@ -781,8 +781,21 @@ __device__ __forceinline__ void push_deferred(const Pools& pl, int q, uint64_t r
     }
 }
 
+// Waves per SIMD the register allocator is asked to fit for the bucketed
+// sweep (more resident waves hide the LDS and DPP latencies of the sweep);
+// chosen per instantiation so that no register spills land in the sweep.
 template <int P, int K, int TIER>
-__global__ __launch_bounds__(64) void subset_kernel(Pools pl) {
+constexpr int min_waves() {
+    if (TIER != kFiltBucket) return 1;
+    if (K <= 8) {
+        if (P <= 5 || (P == 6 && K <= 4)) return 3;
+        return P <= 7 ? 2 : 1;
+    }
+    return P <= 6 ? 2 : 1;
+}
+
+template <int P, int K, int TIER>
+__global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(Pools pl) {
     constexpr int KS = P - 2;
     constexpr int M = 64 * K;
     using Slot = typename SlotOf<P, TIER>::type;
@@ -812,7 +825,6 @@ __global__ __launch_bounds__(64) void subset_kernel(Pools pl) {
     }
     double xd[TIER == kPlain ? K : 1][P];
     float xf[TIER == kPlain ? 1 : K][P];
-    float nr[TIER == kPlain ? 1 : K];
     unsigned long long swept = 0, rechecks = 0, ndefer = 0, ninvalid = 0;
     FiltCtx fc;
     fc.fscale = pl.filter_scale;
@@ -869,7 +881,10 @@ __global__ __launch_bounds__(64) void subset_kernel(Pools pl) {
                         S.f1[c] = (float)Bs.e1[c];
                         S.f2[c] = (float)Bs.e2[c];
                     }
-                    S.beta32 = (float)((((double)P + 3.0) * (double)kU32 + 2.0 * kU64 + Bs.eta) * 1.01);
+                    // per coordinate of a unit-length point: rounding of the
+                    // point and of the basis to float32, p products and sums,
+                    // the float64 centring, and the frame error eta
+                    S.beta32 = (float)((((double)P + 4.0) * (double)kU32 + 4.0 * kU64 + Bs.eta) * 1.01);
                     S64.beta64 = (((double)P + 3.0) * kU64 + Bs.eta) * 1.01;
                     S.state = (Bs.certified && !pl.force_exact) ? 0 : 3;
                 }
@@ -891,12 +906,10 @@ __global__ __launch_bounds__(64) void subset_kernel(Pools pl) {
                     for (int c = 0; c < P; ++c) xd[TIER == kPlain ? i : 0][c] = xb[(size_t)(lane * K + i) * P + c];
             } else {
                 const float* x32 = pl.x32 + d.v_off + opaque;
-                const float* nrm = pl.nrm + d.n_off + opaque;
 #pragma unroll
                 for (int i = 0; i < K; ++i) {
 #pragma unroll
                     for (int c = 0; c < P; ++c) xf[TIER == kPlain ? 0 : i][c] = x32[(size_t)(lane * K + i) * P + c];
-                    nr[TIER == kPlain ? 0 : i] = nrm[lane * K + i];
                 }
             }
             const int cnt = (int)min((uint64_t)64, r1 - rb);
@@ -917,11 +930,11 @@ __global__ __launch_bounds__(64) void subset_kernel(Pools pl) {
                             // exact tier
                             term = kDefer;
                             if (nnz - KS <= 1023)
-                                term = sweep_bucket<P, K>(xf, nr, reinterpret_cast<const SlotFilt<P>&>(S), slots64[s],
+                                term = sweep_bucket<P, K>(xf, reinterpret_cast<const SlotFilt<P>&>(S), slots64[s],
                                                           nnz, fc, hist, glist, sg, rechecks);
                             if (term == kFallback) term = kDefer;
                         } else {
-                            term = sweep_filt<P, K>(xf, nr, reinterpret_cast<const SlotFilt<P>&>(S), slots64[s], nnz,
+                            term = sweep_filt<P, K>(xf, reinterpret_cast<const SlotFilt<P>&>(S), slots64[s], nnz,
                                                     fc, side, sg, rechecks);
                         }
                     }
