@@ -170,6 +170,7 @@ def main():
         "queries_per_s": m / (ms / 1e3),
         "sweeps_per_step": sweeps,
         "fp64_rechecks_per_sweep": st["fp64_rechecks"] / max(1, st["subsets_swept"]),
+        "walked_per_sweep": st["walked_sweeps"] / max(1, st["subsets_swept"]),
         "deferred_subsets": st["deferred_subsets"],
         "exact_predicates": st["exact_predicates"],
         "device_status": st["device_status"],

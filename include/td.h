@@ -111,6 +111,9 @@ typedef struct {
     uint64_t invalid_subsets;    /* subsets with linearly dependent points */
     int32_t device_status;       /* OR of TD_DEV_* over the last call's queries */
     float prep_ms, subset_ms, exact_ms, finalize_ms, total_ms; /* if timing */
+    uint64_t walked_sweeps;      /* bucketed sweeps whose bucket bounds did not
+                                    settle the minimum and that were walked in
+                                    exact order (TD_SWEEP_AUTO) */
 } td_stats;
 
 /* One independent depth problem of a batch (pointers as for td_depth). */

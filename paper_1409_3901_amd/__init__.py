@@ -58,6 +58,7 @@ class Stats(ctypes.Structure):
         ("exact_ms", ctypes.c_float),
         ("finalize_ms", ctypes.c_float),
         ("total_ms", ctypes.c_float),
+        ("walked_sweeps", ctypes.c_uint64),
     ]
 
 

@@ -62,6 +62,7 @@ struct Counters {
     unsigned long long exact_preds;
     unsigned long long degenerate;
     unsigned long long invalid;
+    unsigned long long walked;        // bucketed sweeps that needed the exact walk
     unsigned long long defer_next;    // deferred-queue write position
     unsigned long long prep_next;     // query counter of the preparation kernel
     unsigned long long work_next[kMaxClasses];   // work-item counter per class
@@ -81,6 +82,7 @@ struct CallParams {
 // arrays, xi at 2 * v_off; QueryDesc::n_off in points for nrm).
 struct Pools {
     double* x64;        // centred points, float64, AoS [M][p]
+    double* x64lo;      // remainders: x64 + x64lo = X - z exactly (same layout)
     float* x32;         // centred points, float32, AoS [M][p]
     float* nrm;         // upper bound of ||x||_2 per point [M]
     uint64_t* xi;       // exact integers (x - z) * 2^-E, two's complement

@@ -492,6 +492,153 @@ __device__ __forceinline__ void build_basis(const double (&A)[P][P > 2 ? P - 2 :
     finish_basis<P>(g1, g2, E1, E2, B);
 }
 
+// ------------------------------------ double-double refinement of the basis
+// When the float64 minors cancel badly (strongly anisotropic data), the frame
+// error eta is too large for the filters to decide anything.  The minors are
+// then recomputed in double-double arithmetic from the exact centred values
+// x = hi + lo (prep stores the remainder of the float64 subtraction), with an
+// absolute error below gamma_dd * prod of the column 1-norms.
+struct DD {
+    double hi, lo;
+};
+
+// Error-free transformations need every operation rounded on its own:
+// floating-point contraction (a*b + c fused into one FMA) is switched off in
+// these helpers, where the compiler would otherwise fuse the product of
+// dd_mul into the sum that follows it.
+__device__ __forceinline__ DD dd_two_sum(double a, double b) {
+#pragma clang fp contract(off)
+    const double s = a + b;
+    const double z = s - a;
+    return DD{s, (a - (s - z)) + (b - z)};
+}
+
+// (ah + al) * (x.hi + x.lo): exact leading product by FMA, cross terms
+// rounded, al * x.lo dropped; absolute error <= 5 u^2 |a| |x|
+__device__ __forceinline__ DD dd_mul(double ah, double al, DD x) {
+#pragma clang fp contract(off)
+    const double p = ah * x.hi;
+    const double e = fma(ah, x.hi, -p);
+    const double t = fma(ah, x.lo, fma(al, x.hi, e));
+    return dd_two_sum(p, t);
+}
+
+// absolute error <= 6 u^2 (|x| + |y|)
+__device__ __forceinline__ DD dd_add(DD x, DD y) {
+#pragma clang fp contract(off)
+    const DD s = dd_two_sum(x.hi, y.hi);
+    return dd_two_sum(s.hi, s.lo + x.lo + y.lo);
+}
+
+// Bound factor of a k x k minor by the Laplace recursion in double-double:
+// level c adds at most (5 + 6c) u^2 times the column-norm product.
+template <int KS>
+constexpr double dd_gamma() {
+    double g = 0.0;
+    for (int c = 2; c <= KS; ++c) g += 5.0 + 6.0 * c;
+    return (g + 8.0) * kU64 * kU64 * 1.01;
+}
+
+// The (p-2)-minor of the subset matrix with rows ra and rb left out, in
+// double-double: Laplace recursion along the columns, one column of entries
+// (float64 value and remainder) loaded per level.
+template <int P>
+__device__ __forceinline__ DD dd_minor(const double* x64, const double* x64lo, const int* cc, int ra, int rb) {
+    constexpr int KS = P - 2;
+    constexpr ComboTab<KS> T = make_combo_tab<KS>();
+    const int r0 = min(ra, rb), r1 = max(ra, rb);
+    DD pv[10];
+#pragma unroll
+    for (int r = 0; r < KS; ++r) {
+        const int row = r < r0 ? r : (r + 1 < r1 ? r + 1 : r + 2);
+        pv[r] = DD{x64[(size_t)cc[0] * P + row], x64lo[(size_t)cc[0] * P + row]};
+    }
+#pragma unroll
+    for (int c = 2; c <= KS; ++c) {
+        double ch[KS], cl[KS];
+#pragma unroll
+        for (int r = 0; r < KS; ++r) {
+            const int row = r < r0 ? r : (r + 1 < r1 ? r + 1 : r + 2);
+            ch[r] = x64[(size_t)cc[c - 1] * P + row];
+            cl[r] = x64lo[(size_t)cc[c - 1] * P + row];
+        }
+        DD cv[10];
+#pragma unroll
+        for (int t = 0; t < T.cnt[c]; ++t) {
+            DD v = DD{0.0, 0.0};
+#pragma unroll
+            for (int pos = 0; pos < c; ++pos) {
+                const int row = T.rows[c][t][pos];
+                DD term = dd_mul(ch[row], cl[row], pv[T.child[c][t][pos]]);
+                if ((pos + c - 1) & 1) term = DD{-term.hi, -term.lo};
+                v = dd_add(v, term);
+            }
+            cv[t] = v;
+        }
+#pragma unroll
+        for (int t = 0; t < T.cnt[c]; ++t) pv[t] = cv[t];
+    }
+    return pv[0];
+}
+
+// Recompute the Pluecker rows of the pivot pair (j, k) chosen by the float64
+// pass in double-double and rebuild the basis; per-entry errors are the
+// double-double bound plus the dropped low word.  Supported for p <= 6.
+template <int P>
+__device__ __noinline__ void refine_basis_dd(const double* x64, const double* x64lo, const int* cc, Basis<P>& B) {
+    constexpr int KS = P - 2;
+    if constexpr (KS < 1 || KS > 4) {
+        return;
+    } else {
+        double colprod = 1.0;
+#pragma unroll
+        for (int c = 0; c < KS; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < P; ++r)
+                s += fabs(x64[(size_t)cc[c] * P + r]) + fabs(x64lo[(size_t)cc[c] * P + r]);
+            colprod *= s * (1.0 + 4.0 * P * kU64);
+        }
+        const double emin = dd_gamma<KS>() * colprod;
+        const int bj = B.j, bk = B.k;
+        double g1[P], g2[P], E1[P], E2[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            g1[i] = 0.0;
+            E1[i] = 0.0;
+            g2[i] = 0.0;
+            E2[i] = 0.0;
+        }
+        double om = 0.0, om_err = 0.0;
+        // one rolled loop over the 2p minors (the row index is uniform, so
+        // the register arrays are indexed without memory)
+#pragma unroll 1
+        for (int u = 0; u < 2 * P; ++u) {
+            const int i = u >> 1;
+            const int piv = (u & 1) ? bk : bj;
+            if (i == piv) continue;
+            const DD m = dd_minor<P>(x64, x64lo, cc, i, piv);
+            const int ii = i - (i > piv ? 1 : 0);
+            const double g = ((piv + ii + 1) & 1) ? -m.hi : m.hi;
+            const double e = emin + fabs(m.lo);
+            if (u & 1) {
+                g2[i] = g;
+                E2[i] = e;
+            } else {
+                g1[i] = g;
+                E1[i] = e;
+                if (i == bk) {
+                    om = fabs(m.hi);
+                    om_err = e;
+                }
+            }
+        }
+        B.certified = om > om_err;
+        B.anynz = om > 0.0;
+        finish_basis<P>(g1, g2, E1, E2, B);
+    }
+}
+
 // ------------------------------------------------------- exact 128-bit input
 __device__ __forceinline__ int low_exp(double v) {
     // exponent of the lowest set bit of a finite nonzero double

@@ -80,6 +80,7 @@ struct Workspace {
     int device = -1;
     hipStream_t stream = nullptr;
     double* x64 = nullptr;
+    double* x64lo = nullptr;
     float* x32 = nullptr;
     uint64_t* xi = nullptr;
     size_t val_cap = 0;         // values (points * p)
@@ -154,17 +155,20 @@ td_status grow(Workspace* w, T** p, size_t* cap, size_t need) {
 }
 
 td_status ensure_values(Workspace* w, size_t need) {
-    if (w->val_cap >= need && w->x64) return TD_OK;
+    if (w->val_cap >= need && w->x64 && w->x64lo) return TD_OK;
     size_t nc = std::max(need, w->val_cap * 3 / 2);
     hipFree(w->x64);
+    hipFree(w->x64lo);
     hipFree(w->x32);
     hipFree(w->xi);
     w->x64 = nullptr;
+    w->x64lo = nullptr;
     w->x32 = nullptr;
     w->xi = nullptr;
     w->val_cap = 0;
     ++w->generation;
     if (hipMalloc(&w->x64, nc * sizeof(double)) != hipSuccess) return TD_ERR_OUT_OF_MEMORY;
+    if (hipMalloc(&w->x64lo, nc * sizeof(double)) != hipSuccess) return TD_ERR_OUT_OF_MEMORY;
     if (hipMalloc(&w->x32, nc * sizeof(float)) != hipSuccess) return TD_ERR_OUT_OF_MEMORY;
     if (hipMalloc(&w->xi, nc * 2 * sizeof(uint64_t)) != hipSuccess) return TD_ERR_OUT_OF_MEMORY;
     w->val_cap = nc;
@@ -191,6 +195,7 @@ void free_workspace(Workspace* w) {
     if (!w) return;
     if (w->graph_exec) hipGraphExecDestroy(w->graph_exec);
     hipFree(w->x64);
+    hipFree(w->x64lo);
     hipFree(w->x32);
     hipFree(w->xi);
     hipFree(w->nrm);
@@ -489,6 +494,7 @@ td_status run(const Problem* probs, int num, const td_options& o, hipStream_t st
     Pools pl;
     std::memset(&pl, 0, sizeof(pl));
     pl.x64 = w->x64;
+    pl.x64lo = w->x64lo;
     pl.x32 = w->x32;
     pl.nrm = w->nrm;
     pl.xi = w->xi;
@@ -631,6 +637,7 @@ td_status td_get_stats(td_stats* out) {
     out->exact_predicates = c.exact_preds;
     out->degenerate_subsets = c.degenerate;
     out->invalid_subsets = c.invalid;
+    out->walked_sweeps = c.walked;
     std::vector<QueryState> qs(g_last.nq);
     if (g_last.nq > 0) HIPCHK(hipMemcpy(qs.data(), w->qs, qs.size() * sizeof(QueryState), hipMemcpyDeviceToHost));
     int dst = 0;

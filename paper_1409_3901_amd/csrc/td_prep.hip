@@ -18,7 +18,7 @@ __global__ void init_kernel(Counters* ctr) {
 // query (Section 2: x_i = X_i - z), drop the observations equal to it (they
 // lie on every hyperplane through z and add n0 to every count), and store
 // the nonzero points compacted in input order:
-//   x64 : float64 centred values (one rounding),
+//   x64 : float64 centred values (one rounding), x64lo: the remainder,
 //   x32 : float32 copies scaled to unit length,
 //   nrm : float32 upper bound of ||x||_2 of the float64 values,
 //   xi  : exact integers (X - z) * 2^-E, E the lowest bit exponent over the
@@ -103,6 +103,7 @@ __global__ __launch_bounds__(256) void prep_kernel(Pools pl) {
         __syncthreads();
         const int nnz = s_red[3];
         double* x64 = pl.x64 + d.v_off;
+        double* x64lo = pl.x64lo + d.v_off;
         float* x32 = pl.x32 + d.v_off;
         float* nrm = pl.nrm + d.n_off;
         uint64_t* xi = pl.xi + d.v_off * 2;
@@ -112,6 +113,7 @@ __global__ __launch_bounds__(256) void prep_kernel(Pools pl) {
             if (i >= nnz) {
                 for (int c = 0; c < p; ++c) {
                     x64[(size_t)i * p + c] = 0.0;
+                    x64lo[(size_t)i * p + c] = 0.0;
                     x32[(size_t)i * p + c] = 0.0f;
                     xi[((size_t)i * p + c) * 2] = 0;
                     xi[((size_t)i * p + c) * 2 + 1] = 0;
@@ -135,8 +137,12 @@ __global__ __launch_bounds__(256) void prep_kernel(Pools pl) {
             // error radius the same for every point
             const double inv = 1.0 / sqrt(ss);
             for (int c = 0; c < p; ++c) {
+#pragma clang fp contract(off)
                 const double xv = d.X[(size_t)i * p + c];
                 const double v = xv - s_z[c];
+                // exact remainder of the subtraction (TwoSum of xv and -z)
+                const double zz = v - xv;
+                x64lo[(size_t)j * p + c] = (xv - (v - zz)) + (-s_z[c] - zz);
                 x64[(size_t)j * p + c] = v;
                 x32[(size_t)j * p + c] = (float)(v * inv);
                 uint64_t lo = 0, hi = 0;

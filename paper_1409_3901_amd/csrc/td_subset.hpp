@@ -471,7 +471,8 @@ __device__ __forceinline__ bool bucket_key64(double d1, double d2, double eps64,
 template <int P, int K>
 __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
                             const SlotF64<P>& S64, int nnz, const FiltCtx& fc, uint32_t* hist, uint4* list,
-                            const Staging& sg, unsigned long long& rechecks) {
+                            const Staging& sg, int ubound, unsigned long long& rechecks,
+                            unsigned long long& walked) {
     using G = BucketGeom<K>;
     constexpr int KS = P - 2;
     constexpr int NB = G::NB;
@@ -524,12 +525,17 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
         weak |= (valid && !ok) ? (1u << i) : 0u;
         vmask |= valid ? (1u << i) : 0u;
     }
+    // Points that float64 cannot place either (near the fold line, or inside
+    // span(x_I)) are left out of the sweep; `partial` records it.  Leaving
+    // points out lowers every count, and delta_I >= 0, so the bounds of the
+    // remaining points still bound delta_I + b_I from below.
+    bool partial = false;
     if (__any(weak != 0)) {
         // float32 cannot settle the fold or the key: float64 re-check through
         // the staging arrays (rolled loop, rare path)
         uint32_t* wq = sg.pkey + lane * K;
         int* wa = sg.pS + lane * K;
-        int defer = 0;
+        uint32_t lost = 0;
 #pragma unroll 1
         for (int i = 0; i < K; ++i) {
             if (!((weak >> i) & 1u)) continue;
@@ -542,16 +548,17 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
                 wq[i] = q2;
                 wa[i] = (int)a2;
             } else {
-                defer = 1;
+                lost |= 1u << i;
             }
         }
-        if (__any(defer)) return kDefer;
 #pragma unroll
         for (int i = 0; i < K; ++i)
             if ((weak >> i) & 1u) {
                 qk[i] = wq[i];
                 aux[i] = (uint32_t)wa[i];
             }
+        vmask &= ~lost;
+        partial = __any(lost != 0);
     }
     // histogram, branch-free: points that are not swept add 0 to a word of
     // their own lane past the buckets (hist holds NB + 64 words)
@@ -599,7 +606,15 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     }
     U = wave_min_dpp(U);
     L = wave_min_dpp(L);
-    if (L >= U) return U;
+    // With points left out, only the lower bound holds: a subset that cannot
+    // go below `ubound` (a term the query already reached) is not needed,
+    // anything else goes to the exact tier.
+    if (partial) return L >= ubound ? kSkip : kDefer;
+    // Done when L = U; also when L is not below `ubound`: then no state of
+    // this sweep can lower the minimum over subsets, and U (>= b_I >= L) is
+    // returned in place of b_I.
+    if (L >= U || L >= ubound) return U;
+    ++walked;
 
     // ---- rare: walk the runs whose range dips below U in exact order.
     // Run info per bucket: (first bucket of its run << 11) | state at the
@@ -702,7 +717,16 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
                     hn |= (vb.y & kAuxNeg) ? 1 : 0;
                 }
                 const int c = b - a + 1;
-                if (hp && hn) {
+                // states inside the run lie in [s - (pos in run), s + (neg in
+                // run)]: if min(S, m - S) cannot go below the bound there, the
+                // inner order does not matter
+                int npos_c = 0;
+                for (int u = a; u <= b; ++u) npos_c += (list[u].y & kAuxNeg) ? 0 : 1;
+                const int dip = min(s - npos_c, m - (s + (c - npos_c)));
+                const bool needed = dip < min(min(U, ubound), best);
+                if (hp && hn && !needed) {
+                    s += c - 2 * npos_c;
+                } else if (hp && hn) {
                     // both fold signs inside uncertain order: float64 keys,
                     // insertion-sorted in the block's staging arrays
                     if (c > kClusterMax) { defer = 1; break; }
@@ -729,24 +753,35 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
                     }
                     rechecks += (unsigned long long)c;
                     if (!ok) { defer = 1; break; }
+                    // float64 sub-runs of overlapping intervals; one that holds
+                    // both signs is settled only if its states could go below
+                    // the bound (then the subset goes to the exact tier)
                     double thi = rt[0] + (double)fabsf(rr[0]);
-                    int sp = rr[0] < 0.0f, sn = rr[0] > 0.0f;
+                    int s_sub = s, np_sub = 0, nn_sub = 0;
+                    if (rr[0] < 0.0f) ++nn_sub; else ++np_sub;
                     s += (rr[0] < 0.0f) ? 1 : -1;
 #pragma unroll 1
                     for (int u = 1; u < c; ++u) {
                         const double tu = rt[u];
                         const float ru = rr[u];
                         if (tu - (double)fabsf(ru) > thi) {
-                            if (sp && sn) { ok = false; break; }
+                            if (np_sub && nn_sub &&
+                                min(s_sub - np_sub, m - (s_sub + nn_sub)) < min(min(U, ubound), best)) {
+                                ok = false;
+                                break;
+                            }
                             best = min(best, fside(s, m));
-                            sp = sn = 0;
+                            s_sub = s;
+                            np_sub = nn_sub = 0;
                         }
-                        sp |= ru < 0.0f;
-                        sn |= ru > 0.0f;
+                        if (ru < 0.0f) ++nn_sub; else ++np_sub;
                         thi = fmax(thi, tu + (double)fabsf(ru));
                         s += (ru < 0.0f) ? 1 : -1;
                     }
-                    if (!ok || (sp && sn)) { defer = 1; break; }
+                    if (ok && np_sub && nn_sub &&
+                        min(s_sub - np_sub, m - (s_sub + nn_sub)) < min(min(U, ubound), best))
+                        ok = false;
+                    if (!ok) { defer = 1; break; }
                 } else {
                     s += hn ? c : -c;
                 }
@@ -825,7 +860,7 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
     }
     double xd[TIER == kPlain ? K : 1][P];
     float xf[TIER == kPlain ? 1 : K][P];
-    unsigned long long swept = 0, rechecks = 0, ndefer = 0, ninvalid = 0;
+    unsigned long long swept = 0, rechecks = 0, ndefer = 0, ninvalid = 0, nwalked = 0;
     FiltCtx fc;
     fc.fscale = pl.filter_scale;
     const uint64_t cbeg = pl.cp->cls_begin[pl.cls];
@@ -850,6 +885,10 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
         fc.nrm = pl.nrm + d.n_off;
         fc.idx_bits = d.idx_bits;
         int wbest = kBig;
+        // running minimum of the query (terms of other work items so far)
+        int qbest = kBig;
+        if constexpr (BUCKET)
+            qbest = uni(__hip_atomic_load(&pl.qs[q].min_term, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         for (uint64_t rb = r0; rb < r1; rb += 64) {
             const uint64_t myr = rb + (uint64_t)lane;
             Slot& my = slots[lane];
@@ -864,6 +903,11 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
                     for (int r = 0; r < P; ++r) A[r][col] = x64[(size_t)cc[col] * P + r];
                 Basis<P> Bs;
                 build_basis<P>(A, Bs);
+                if constexpr (TIER != kPlain) {
+                    // float64 minors that cancel badly: double-double rows
+                    if (!Bs.certified || Bs.eta > 0x1p-30)
+                        refine_basis_dd<P>(x64, pl.x64lo + d.v_off, cc, Bs);
+                }
 #pragma unroll
                 for (int col = 0; col < KS; ++col) my.mem[col] = (int16_t)cc[col];
                 if constexpr (TIER == kPlain) {
@@ -931,7 +975,8 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
                             term = kDefer;
                             if (nnz - KS <= 1023)
                                 term = sweep_bucket<P, K>(xf, reinterpret_cast<const SlotFilt<P>&>(S), slots64[s],
-                                                          nnz, fc, hist, glist, sg, rechecks);
+                                                          nnz, fc, hist, glist, sg, min(qbest, wbest), rechecks,
+                                                          nwalked);
                             if (term == kFallback) term = kDefer;
                         } else {
                             term = sweep_filt<P, K>(xf, reinterpret_cast<const SlotFilt<P>&>(S), slots64[s], nnz,
@@ -942,6 +987,10 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
                 if (term == kDefer) {
                     if (lane == 0) push_deferred<P>(pl, q, rb + (uint64_t)s);
                     ++ndefer;
+                    continue;
+                }
+                if (term == kSkip) {   // bounded below by a term already reached
+                    ++swept;
                     continue;
                 }
                 ++swept;
@@ -960,6 +1009,7 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
         if (rc) atomicAdd(&pl.ctr->fp64_rechecks, rc);
         if (ndefer) atomicAdd(&pl.ctr->deferred, ndefer);
         if (ninvalid) atomicAdd(&pl.ctr->invalid, ninvalid);
+        if (nwalked) atomicAdd(&pl.ctr->walked, nwalked);
     }
 }
 

@@ -37,7 +37,7 @@ def test_struct_layouts_match_header():
     # sizeof(td_options), sizeof(td_problem), sizeof(td_stats) on x86-64
     assert ctypes.sizeof(td.Options) == 48
     assert ctypes.sizeof(td.Problem) == 48
-    assert ctypes.sizeof(td.Stats) == 72
+    assert ctypes.sizeof(td.Stats) == 80
 
 
 def test_status_strings_and_version(lib):

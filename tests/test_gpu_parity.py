@@ -170,3 +170,25 @@ def test_every_sample_point(td, dev, prec, p, n):
     exp = oracle.depth_counts(X, X)
     assert np.array_equal(got, exp), (int(np.sum(got != exp)),)
     assert np.all(got >= 1)
+
+
+@pytest.mark.parametrize("prec", ["filtered", "bitonic"])
+def test_c5_affine_invariance_full_size(td, dev, prec):
+    """The precision stress workload at full size (p = 6, n = 200, all 16
+    queries) against a property that holds at any size: the depth is
+    invariant under the exact integer affine map that produced the data
+    (Section 1), so the counts on the mapped data (coordinates up to ~1e15,
+    where float32 rounding is real) must equal the counts on the pre-map
+    lattice (small integers, exact in float32)."""
+    X, Z, info = workloads.c5(return_premap=True)
+    X0 = info["X0"].astype(np.float64)
+    Z0 = info["Z0"].astype(np.float64)
+    a = run(td, dev, X, Z, **PREC_OPTS[prec])
+    sa = td.get_stats()
+    b = run(td, dev, X0, Z0, **PREC_OPTS[prec])
+    sb = td.get_stats()
+    print("c5", prec, a.tolist(), "deferred", sa["deferred_subsets"], sb["deferred_subsets"])
+    assert sa["device_status"] == 0 and sb["device_status"] == 0
+    assert np.array_equal(a, b), (a.tolist(), b.tolist())
+    n0 = np.array([int(np.sum(np.all(X == z, axis=1))) for z in Z])
+    assert np.all(a >= n0) and np.all(a <= n0 + (X.shape[0] - n0) // 2)
