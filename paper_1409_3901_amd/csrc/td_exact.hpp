@@ -317,6 +317,7 @@ __global__ __launch_bounds__(64) void exact_kernel(Pools pl) {
             for (int r = 0; r < P; ++r) A[r][col] = x64[(size_t)mem[col] * P + r];
         Basis<P> Bs;
         build_basis<P>(A, Bs);
+        if (!Bs.certified || Bs.eta > 0x1p-30) refine_basis_dd<P>(x64, pl.x64lo + d.v_off, mem, Bs);
         const bool ints_ok = !(st.status & kStNoExactInts);
         bool have_rows = false;
         if (!Bs.certified) {
@@ -384,6 +385,59 @@ __global__ __launch_bounds__(64) void exact_kernel(Pools pl) {
                 weak |= 1u << i;
             }
         }
+        // ---- lower bound from the points float64 places.  Every other point
+        // only adds to the counts and delta_I >= 0, so when the smallest state
+        // the certified points allow (runs of overlapping intervals in any
+        // inner order) is not below a term the query already reached, the
+        // subset cannot lower the minimum: no exact work is done for it.
+        const int qbest = uni(__hip_atomic_load(&pl.qs[q].min_term, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (qbest < 0x7fffffff) {
+            uint64_t kb[K];
+#pragma unroll
+            for (int i = 0; i < K; ++i) kb[i] = key[i];
+            wave_sort<K>(kb);
+#pragma unroll
+            for (int i = 0; i < K; ++i) skey[lane * K + i] = kb[i];
+            int mc = 0;
+#pragma unroll
+            for (int i = 0; i < K; ++i) mc += (key[i] != ~0ull) ? 1 : 0;
+            const int mcert = wave_sum(mc);
+            const int S0c = wave_sum(nplus);
+            __syncthreads();
+            int lb = 0;
+            if (lane == 0) {
+                int S = S0c;
+                lb = fside(S0c, mcert);
+                int i = 0;
+#pragma unroll 1
+                while (i < mcert) {
+                    const uint64_t k0 = skey[i];
+                    const uint32_t sd0 = sside[k0 & 1023u];
+                    int64_t mhi = (int64_t)(k0 >> 10) + (int64_t)(sd0 & 0x7fffffffu);
+                    int np = (sd0 >> 31) ? 0 : 1;
+                    int j = i;
+                    while (j + 1 < mcert) {
+                        const uint64_t kk = skey[j + 1];
+                        const uint32_t sd = sside[kk & 1023u];
+                        if ((int64_t)(kk >> 10) - (int64_t)(sd & 0x7fffffffu) > mhi) break;
+                        mhi = max(mhi, (int64_t)(kk >> 10) + (int64_t)(sd & 0x7fffffffu));
+                        np += (sd >> 31) ? 0 : 1;
+                        ++j;
+                    }
+                    const int c = j - i + 1;
+                    lb = min(lb, min(S - np, mcert - (S + (c - np))));
+                    S += c - 2 * np;
+                    lb = min(lb, fside(S, mcert));
+                    i = j + 1;
+                }
+            }
+            lb = __builtin_amdgcn_readfirstlane(lb);
+            __syncthreads();
+            if (lb >= qbest) {
+                ++swept;
+                continue;
+            }
+        }
         if (lane == 0) { s_nextra = 0; s_flag = 0; }
         if (__any(weak != 0)) {
             if (!ints_ok) {
@@ -436,11 +490,15 @@ __global__ __launch_bounds__(64) void exact_kernel(Pools pl) {
         }
         __syncthreads();
         const int nextra = uni(s_nextra);
-        if (nextra > kDeltaMax - KS || uni(s_flag) != 0) {
+        if (uni(s_flag) != 0) {
             if (lane == 0) atomicOr(&pl.qs[q].status, kStDegenLimit);
             __syncthreads();
             continue;
         }
+        // more points inside span(x_I) than the hitting-set search takes:
+        // b_I is still computed; delta_I is needed only if b_I alone is below
+        // the query's running minimum (otherwise the subset cannot lower it)
+        const bool delta_over = nextra > kDeltaMax - KS;
         wave_sort<K>(key);
 #pragma unroll
         for (int i = 0; i < K; ++i) skey[lane * K + i] = key[i];
@@ -518,7 +576,14 @@ __global__ __launch_bounds__(64) void exact_kernel(Pools pl) {
                 i = j + 1;
             }
             term = best;
-            if (nextra > 0 && !status) {
+            // delta_I >= 0: when b_I alone is not below the query's running
+            // minimum the subset cannot lower it, and delta_I is not computed
+            const int qb = __hip_atomic_load(&pl.qs[q].min_term, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (nextra > 0 && !status && term >= qb) {
+                term = 0x7fffffff;
+            } else if (delta_over && !status) {
+                status |= kStDegenLimit;
+            } else if (nextra > 0 && !status) {
                 int kidx[kDeltaMax];
                 for (int c2 = 0; c2 < KS; ++c2) kidx[c2] = mem[c2];
                 for (int e2 = 0; e2 < nextra; ++e2) kidx[KS + e2] = s_extra[e2];
