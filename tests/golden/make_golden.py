@@ -6,8 +6,10 @@ resumable: each finished query is saved at once, and queries already present
 are skipped.
 
     python tests/golden/make_golden.py [c1 c2 c3 c5 c4] [--threads T]
+    python tests/golden/make_golden.py c5 --queries 15,14,13 --part b
 
-Files: ``tests/golden/<config>.json`` holding
+Files: ``tests/golden/<config>.json`` (and ``<config>.<part>.json`` for shares
+of the queries computed by another process, merged by the readers) holding
 ``{"config", "seed", "source", "n", "p", "counts": {query_index: count}}``;
 for c4 the counts are keyed ``"<dataset>:<query>"`` and only a seeded
 subsample (queries of datasets whose per-query cost C(n, p-2) * n is at most
@@ -59,8 +61,8 @@ def _save(path, obj):
     os.replace(tmp, path)
 
 
-def run(cfg: str, threads: int):
-    path = os.path.join(HERE, cfg + ".json")
+def run(cfg: str, threads: int, queries=None, part=None):
+    path = os.path.join(HERE, cfg + (".%s" % part if part else "") + ".json")
     obj = _load(path)
     if cfg == "c4":
         data = workloads.c4()
@@ -82,7 +84,7 @@ def run(cfg: str, threads: int):
     if obj is None:
         obj = {"config": cfg, "seed": SEEDS[cfg], "source": "oracle/td_oracle.cpp",
                "n": int(X.shape[0]), "p": int(X.shape[1]), "counts": {}}
-    order = list(range(Z.shape[0]))
+    order = list(range(Z.shape[0])) if queries is None else list(queries)
     for q in order:
         if str(q) in obj["counts"]:
             continue
@@ -97,10 +99,16 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("configs", nargs="*", default=["c1", "c2", "c3", "c5", "c4"])
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--queries", default=None,
+                    help="query indices in the order to compute, e.g. 15,14,13 (single config)")
+    ap.add_argument("--part", default=None,
+                    help="write <config>.<part>.json instead (a disjoint share of the queries, "
+                         "computed by a second process); readers merge the parts")
     a = ap.parse_args()
     oracle.build(force=False)
+    qs = [int(v) for v in a.queries.split(",")] if a.queries else None
     for cfg in a.configs:
-        run(cfg, a.threads or oracle.default_threads())
+        run(cfg, a.threads or oracle.default_threads(), qs, a.part)
 
 
 if __name__ == "__main__":

@@ -98,10 +98,21 @@ def test_outside_hull_zero(td, dev, prec):
 
 
 def _stored(cfg):
-    path = os.path.join(GOLD, cfg + ".json")
-    if not os.path.exists(path):
+    """Stored oracle counts of a workload, merged over the main file and the
+    shares written by other generator processes (<cfg>.<part>.json)."""
+    import glob
+    paths = sorted(glob.glob(os.path.join(GOLD, cfg + ".json")) + glob.glob(os.path.join(GOLD, cfg + ".*.json")))
+    if not paths:
         return None
-    return golden(cfg)
+    merged = None
+    for path in paths:
+        with open(path) as f:
+            g = json.load(f)
+        if merged is None:
+            merged = g
+        else:
+            merged["counts"].update(g["counts"])
+    return merged
 
 
 @pytest.mark.parametrize("prec", PRECS)
