@@ -705,7 +705,7 @@ td_status td_autotune(int32_t p, int64_t n, const td_options* base, void* stream
     float best = 1e30f;
     Shape bs;
     const int chunks[] = {64, 128, 256, 512};
-    const int grids[] = {2, 4, 8, 16};
+    const int grids[] = {4, 8, 12, 16};   // resident waves per CU: up to 3 per SIMD
     for (int ci = 0; ci < 4 && ret == TD_OK; ++ci)
         for (int gi = 0; gi < 4 && ret == TD_OK; ++gi) {
             td_options t = o;

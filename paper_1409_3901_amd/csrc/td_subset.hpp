@@ -422,7 +422,7 @@ __device__ int sweep_filt(const float (&xr)[K][P], const SlotFilt<P>& S,
 // pseudo-angle) and refined exactly only where the minimum may lie.
 //
 // Keys: t' in [0, 2] maps to q = t' QS + W - QS ... in quanta, q in
-// [W, (NB - 1) W], with NB = M buckets of W = 2^31 / NB quanta.  Every point
+// [W, (NB - 1) W], with NB buckets (M/2) of W = 2^31 / NB quanta.  Every point
 // carries a certified interval [q - rq, q + rq] (rq < W / 4) that contains the
 // key of the exact frame, so a bucket boundary that no interval crosses is a
 // strict gap of the angular order, and the state there is a state of the
@@ -443,10 +443,18 @@ constexpr uint32_t kHistStr = 1u << 22;
 constexpr uint32_t kAuxNeg = 1u << 31;
 constexpr int kListMax = 128;   // gathered points of the runs walked exactly
 
+// Buckets per lane: half the points per lane (about two points per bucket).
+// The bounds L and U only decide when a sweep must be walked in exact order,
+// and with the running-minimum bound that is rare, so fewer, wider buckets
+// cost little there and halve the scan.
+template <int K>
+constexpr int buckets_per_lane() { return K >= 2 ? K / 2 : 1; }
+
 template <int K>
 struct BucketGeom {
-    static constexpr int NB = 64 * K;
-    static constexpr int LOGNB = 6 + (K >= 2) + (K >= 4) + (K >= 8) + (K >= 16);
+    static constexpr int NBL = buckets_per_lane<K>();
+    static constexpr int NB = 64 * NBL;
+    static constexpr int LOGNB = 6 + (NBL >= 2) + (NBL >= 4) + (NBL >= 8) + (NBL >= 16);
     static constexpr int SH = 31 - LOGNB;
     static constexpr uint32_t W = 1u << SH;
     static constexpr double QS = (double)(NB - 2) * (double)W / 2.0;   // quanta per unit of t'
@@ -476,6 +484,7 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     using G = BucketGeom<K>;
     constexpr int KS = P - 2;
     constexpr int NB = G::NB;
+    constexpr int NBL = G::NBL;
     const int lane = lane_id();
     const float QSf = (float)G::QS;
     const float QBf = (float)(G::QS + (double)G::W);
@@ -560,8 +569,9 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
         vmask &= ~lost;
         partial = __any(lost != 0);
     }
-    // histogram, branch-free: points that are not swept add 0 to a word of
-    // their own lane past the buckets (hist holds NB + 64 words)
+    // histogram, branch-free: points that are not swept add to a word of
+    // their own lane past the buckets (hist holds NB + 64 words, the extra
+    // ones are never read)
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const uint32_t rq = aux[i] & 0x7fffffffu;
@@ -569,18 +579,18 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
         // crossing count field: 1 when the interval ends in the next bucket
         const uint32_t inc = ((aux[i] & kAuxNeg) ? kHistNeg : kHistPos) | ((((qk[i] + rq) >> G::SH) - blo) << 22);
         const bool v = (vmask >> i) & 1u;
-        atomicAdd(&hist[v ? (blo & (NB - 1)) : (uint32_t)(NB + lane)], v ? inc : 0u);
+        atomicAdd(&hist[v ? (blo & (NB - 1)) : (uint32_t)(NB + lane)], inc);
     }
     __syncthreads();
     // scan of the lane's K buckets [lane K, lane K + K)
-    uint32_t w[K];
+    uint32_t w[NBL];
 #pragma unroll
-    for (int j = 0; j < K; ++j) w[j] = hist[lane * K + j];
+    for (int j = 0; j < NBL; ++j) w[j] = hist[lane * NBL + j];
 #pragma unroll
-    for (int j = 0; j < K; ++j) hist[lane * K + j] = 0u;
+    for (int j = 0; j < NBL; ++j) hist[lane * NBL + j] = 0u;
     uint32_t tl = 0;
 #pragma unroll
-    for (int j = 0; j < K; ++j) tl += w[j];
+    for (int j = 0; j < NBL; ++j) tl += w[j];
     tl &= 0x3fffffu;   // per-field sums stay below 2^11: no carry between fields
     const int incl = wave_incl_sum_dpp((int)tl);
     const int pre = incl - (int)tl;
@@ -590,12 +600,12 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     const int Sst = S0 - (pre & 0x7ff) + ((pre >> 11) & 0x7ff);
     // crossings into this lane's first bucket: the previous lane's last
     // bucket (DPP wave_shr:1; lane 0 reads 0)
-    const int cin = lane_prev((int)(w[K - 1] >> 22), 0);
+    const int cin = lane_prev((int)(w[NBL - 1] >> 22), 0);
     int U = kBig, L = kBig;
     {
         int s = Sst;
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
+        for (int j = 0; j < NBL; ++j) {
             const int np = (int)(w[j] & 0x7ffu);
             const int nn = (int)((w[j] >> 11) & 0x7ffu);
             const int c = (j == 0) ? cin : (int)(w[j - 1] >> 22);
@@ -619,17 +629,17 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     // ---- rare: walk the runs whose range dips below U in exact order.
     // Run info per bucket: (first bucket of its run << 11) | state at the
     // run's left boundary; bit 31 of a run's first entry marks it for the walk.
-    int loc[K];
+    int loc[NBL];
     uint32_t hot = 0;
     int last = -1;
     {
         int s = Sst;
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
+        for (int j = 0; j < NBL; ++j) {
             const int np = (int)(w[j] & 0x7ffu);
             const int nn = (int)((w[j] >> 11) & 0x7ffu);
             const int c = (j == 0) ? cin : (int)(w[j - 1] >> 22);
-            if (c == 0) last = ((lane * K + j) << 11) | s;
+            if (c == 0) last = ((lane * NBL + j) << 11) | s;
             loc[j] = last;
             if (min(s - np - c, m - (s + nn + c)) < U) hot |= 1u << j;
             s += nn - np;
@@ -638,14 +648,14 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     {
         const int carry = wave_excl_max(last, -1);   // bucket 0 starts a run: carry >= 0 where needed
 #pragma unroll
-        for (int j = 0; j < K; ++j)
+        for (int j = 0; j < NBL; ++j)
             if (loc[j] < 0) loc[j] = carry;
     }
 #pragma unroll
-    for (int j = 0; j < K; ++j) hist[lane * K + j] = (uint32_t)loc[j];
+    for (int j = 0; j < NBL; ++j) hist[lane * NBL + j] = (uint32_t)loc[j];
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < K; ++j)
+    for (int j = 0; j < NBL; ++j)
         if ((hot >> j) & 1u) atomicOr(&hist[(loc[j] >> 11) & (NB - 1)], 0x80000000u);
     __syncthreads();
     uint32_t gm = 0;
@@ -666,7 +676,7 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     const int gtot = __builtin_amdgcn_readlane(gincl, 63);
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < K; ++j) hist[lane * K + j] = 0u;
+    for (int j = 0; j < NBL; ++j) hist[lane * NBL + j] = 0u;
     if (gtot > kListMax) {
         __syncthreads();
         return kFallback;   // too many points to walk: the caller runs the full sort
@@ -837,7 +847,7 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
     __shared__ Slot slots[64];
     constexpr bool BUCKET = TIER == kFiltBucket;
     __shared__ uint16_t side[TIER == kFilt ? M : 1];
-    __shared__ uint32_t hist[BUCKET ? M + 64 : 1];
+    __shared__ uint32_t hist[BUCKET ? BucketGeom<K>::NB + 64 : 1];
     __shared__ uint4 glist[BUCKET ? kListMax : 1];
     // per-block device scratch: float64 basis slots, then the staging arrays
     uint8_t* wsc = pl.wscratch + pl.cp->cls_scratch[pl.cls] + (uint64_t)blockIdx.x * pl.wscratch_bytes;
@@ -854,8 +864,8 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
     const int lane = lane_id();
     if constexpr (BUCKET) {
 #pragma unroll
-        for (int j = 0; j < K; ++j) hist[lane * K + j] = 0u;
-        hist[M + lane] = 0u;
+        for (int j = 0; j < BucketGeom<K>::NBL; ++j) hist[lane * BucketGeom<K>::NBL + j] = 0u;
+        hist[BucketGeom<K>::NB + lane] = 0u;
         __syncthreads();
     }
     double xd[TIER == kPlain ? K : 1][P];
@@ -905,8 +915,16 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
                 build_basis<P>(A, Bs);
                 if constexpr (TIER != kPlain) {
                     // float64 minors that cancel badly: double-double rows
-                    if (!Bs.certified || Bs.eta > 0x1p-30)
-                        refine_basis_dd<P>(x64, pl.x64lo + d.v_off, cc, Bs);
+                    // (copies, so that only this rare path keeps the basis
+                    // and the subset in memory)
+                    if (!Bs.certified || Bs.eta > 0x1p-30) {
+                        Basis<P> Br = Bs;
+                        int cr[KS > 0 ? KS : 1];
+#pragma unroll
+                        for (int c = 0; c < KS; ++c) cr[c] = cc[c];
+                        refine_basis_dd<P>(x64, pl.x64lo + d.v_off, cr, Br);
+                        Bs = Br;
+                    }
                 }
 #pragma unroll
                 for (int col = 0; col < KS; ++col) my.mem[col] = (int16_t)cc[col];
