@@ -448,7 +448,7 @@ constexpr int kListMax = 128;   // gathered points of the runs walked exactly
 // and with the running-minimum bound that is rare, so fewer, wider buckets
 // cost little there and halve the scan.
 template <int K>
-constexpr int buckets_per_lane() { return K >= 2 ? K / 2 : 1; }
+constexpr int buckets_per_lane() { return K >= 4 ? K / 4 : 1; }
 
 template <int K>
 struct BucketGeom {
