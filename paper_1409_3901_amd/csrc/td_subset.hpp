@@ -422,7 +422,7 @@ __device__ int sweep_filt(const float (&xr)[K][P], const SlotFilt<P>& S,
 // pseudo-angle) and refined exactly only where the minimum may lie.
 //
 // Keys: t' in [0, 2] maps to q = t' QS + W - QS ... in quanta, q in
-// [W, (NB - 1) W], with NB buckets (M/2) of W = 2^31 / NB quanta.  Every point
+// [W, (NB - 1) W], with NB buckets (M/4) of W = 2^31 / NB quanta.  Every point
 // carries a certified interval [q - rq, q + rq] (rq < W / 4) that contains the
 // key of the exact frame, so a bucket boundary that no interval crosses is a
 // strict gap of the angular order, and the state there is a state of the
@@ -443,10 +443,12 @@ constexpr uint32_t kHistStr = 1u << 22;
 constexpr uint32_t kAuxNeg = 1u << 31;
 constexpr int kListMax = 128;   // gathered points of the runs walked exactly
 
-// Buckets per lane: half the points per lane (about two points per bucket).
-// The bounds L and U only decide when a sweep must be walked in exact order,
-// and with the running-minimum bound that is rare, so fewer, wider buckets
-// cost little there and halve the scan.
+// Buckets per lane: a quarter of the points per lane (about four points per
+// bucket).  The bounds L and U only decide when a sweep must be walked in
+// exact order, and with the running-minimum bound that is rare, so fewer,
+// wider buckets cost little there and shorten the scan (measured on p = 5,
+// n = 500: M/4 buckets beat M/2 by a third and match M/8, which walks twice
+// as often).
 template <int K>
 constexpr int buckets_per_lane() { return K >= 4 ? K / 4 : 1; }
 
