@@ -87,8 +87,9 @@ def main():
                          "256*8 plain float64 launches")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the subset loop would shard); run with --gpus 1",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the subset loop would shard by rank ranges of each query, followed by "
+              "one MIN all-reduce of the per-query counts); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

@@ -100,6 +100,15 @@ typedef struct {
     int64_t deferred_capacity; /* max deferred subsets per call, 0 = default */
     int32_t sweep;             /* td_sweep: how the filtered tier orders the
                                   projected points (default TD_SWEEP_AUTO) */
+    int32_t prune;             /* 1 (default): before the subsets, bound the
+                                  minimum by the closed halfspace counts of the
+                                  2n directions +-(X_j - z) (Algorithm 3,
+                                  Step 2(a)), let the bucketed sweep skip
+                                  subsets that cannot go below it, and skip the
+                                  remaining subsets of a query once a term of 0
+                                  is reached; 0: sweep every subset.  The
+                                  counts are the same either way.  Ignored by
+                                  TD_PREC_FP64_PLAIN. */
 } td_options;
 
 typedef struct {
@@ -114,6 +123,8 @@ typedef struct {
     uint64_t walked_sweeps;      /* bucketed sweeps whose bucket bounds did not
                                     settle the minimum and that were walked in
                                     exact order (TD_SWEEP_AUTO) */
+    uint64_t pruned_subsets;     /* subsets skipped because the query's
+                                    minimum had already reached 0 (prune) */
 } td_stats;
 
 /* One independent depth problem of a batch (pointers as for td_depth). */

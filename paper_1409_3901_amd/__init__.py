@@ -41,6 +41,7 @@ class Options(ctypes.Structure):
         ("timing", ctypes.c_int32),
         ("deferred_capacity", ctypes.c_int64),
         ("sweep", ctypes.c_int32),
+        ("prune", ctypes.c_int32),
     ]
 
 
@@ -59,6 +60,7 @@ class Stats(ctypes.Structure):
         ("finalize_ms", ctypes.c_float),
         ("total_ms", ctypes.c_float),
         ("walked_sweeps", ctypes.c_uint64),
+        ("pruned_subsets", ctypes.c_uint64),
     ]
 
 
@@ -120,7 +122,7 @@ def load():
 
 
 def options(precision="filtered", autotune=True, chunk=0, grid_blocks=0, filter_scale=1.0,
-            force_exact=False, timing=False, deferred_capacity=0, sweep="auto") -> Options:
+            force_exact=False, timing=False, deferred_capacity=0, sweep="auto", prune=True) -> Options:
     lib = load()
     o = Options()
     lib.td_default_options(ctypes.byref(o))
@@ -133,6 +135,7 @@ def options(precision="filtered", autotune=True, chunk=0, grid_blocks=0, filter_
     o.timing = 1 if timing else 0
     o.deferred_capacity = int(deferred_capacity)
     o.sweep = SWEEP[sweep] if isinstance(sweep, str) else int(sweep)
+    o.prune = 1 if prune else 0
     return o
 
 

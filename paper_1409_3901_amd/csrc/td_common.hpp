@@ -28,6 +28,8 @@ struct QueryState {
     int32_t n0;         // observations equal to the query
     int32_t status;     // kSt* bits
     int32_t min_term;   // running minimum of delta_I + b_I (atomicMin)
+    int32_t ub_term;    // certified upper bound of the minimum from the
+                        // directions +-x_j (0x7fffffff when not computed)
 };
 
 // Per-query description (one entry per query of every problem in a call).
@@ -63,6 +65,8 @@ struct Counters {
     unsigned long long degenerate;
     unsigned long long invalid;
     unsigned long long walked;        // bucketed sweeps that needed the exact walk
+    unsigned long long pruned;        // subsets of work items skipped once the
+                                      // query's minimum had reached 0
     unsigned long long defer_next;    // deferred-queue write position
     unsigned long long prep_next;     // query counter of the preparation kernel
     unsigned long long work_next[kMaxClasses];   // work-item counter per class
@@ -99,6 +103,8 @@ struct Pools {
     int32_t force_exact;
     int32_t cls;        // class slot of this launch (subset and exact kernels)
     int32_t sweep_mode; // 0: bucketed sweep kernels, 1: full-sort kernels
+    int32_t prune;      // 1: upper bound from the directions +-x_j and skip of
+                        // work items once the minimum is 0 (not in the plain tier)
     uint8_t* wscratch;       // per-block scratch in device memory
     uint64_t wscratch_bytes; // bytes per block
 };

@@ -218,6 +218,7 @@ td_options defaults() {
     o.precision = TD_PREC_FP32_FILTERED;
     o.autotune = 1;
     o.filter_scale = 1.0;
+    o.prune = 1;
     return o;
 }
 
@@ -228,6 +229,7 @@ td_status check_options(const td_options& o) {
     if (!(o.filter_scale >= 0.0)) return TD_ERR_INVALID_ARG;   // rejects NaN
     if (o.deferred_capacity < 0) return TD_ERR_INVALID_ARG;
     if (o.sweep < 0 || o.sweep > 1) return TD_ERR_INVALID_ARG;
+    if (o.prune < 0 || o.prune > 1) return TD_ERR_INVALID_ARG;
     return TD_OK;
 }
 
@@ -415,7 +417,7 @@ std::string graph_signature(const Plan& plan, const Pools& pl, const td_options&
                      std::to_string(plan.prep_blocks) + "|" + std::to_string(plan.fin_blocks) + "|" +
                      std::to_string(pl.force_exact) + "|" + std::to_string(pl.filter_scale) + "|" +
                      std::to_string(pl.chunk) + "|" + std::to_string(pl.defer_cap) + "|" +
-                     std::to_string(pl.sweep_mode);
+                     std::to_string(pl.sweep_mode) + "|" + std::to_string(pl.prune);
     for (const ClassPlan& cp : plan.cls) {
         k += "|" + std::to_string(cp.p) + "," + std::to_string(cp.K) + "," + std::to_string(cp.shape.blocks) + "," +
              std::to_string(cp.scratch_per_block) + "," + std::to_string(cp.items > 0);
@@ -509,6 +511,7 @@ td_status run(const Problem* probs, int num, const td_options& o, hipStream_t st
     pl.filter_scale = std::isinf(o.filter_scale) ? 3.0e38f : (float)o.filter_scale;
     pl.force_exact = (o.force_exact || o.precision == TD_PREC_EXACT) ? 1 : 0;
     pl.sweep_mode = o.sweep;
+    pl.prune = (o.prune && subset_tier(o) != 0) ? 1 : 0;
     pl.wscratch = w->wscratch;
 
     g_last.ws = w;
@@ -638,6 +641,7 @@ td_status td_get_stats(td_stats* out) {
     out->degenerate_subsets = c.degenerate;
     out->invalid_subsets = c.invalid;
     out->walked_sweeps = c.walked;
+    out->pruned_subsets = c.pruned;
     std::vector<QueryState> qs(g_last.nq);
     if (g_last.nq > 0) HIPCHK(hipMemcpy(qs.data(), w->qs, qs.size() * sizeof(QueryState), hipMemcpyDeviceToHost));
     int dst = 0;

@@ -160,6 +160,45 @@ __global__ __launch_bounds__(256) void prep_kernel(Pools pl) {
             // of the sum, the square root and the conversion to float32
             nrm[j] = (float)(sqrt(ss) * (1.0 + 1e-6));
         }
+        // Upper bound of the minimum from the 2n' directions +-x_j (Algorithm
+        // 3, Step 2(a)): the depth is at most the closed halfspace count of
+        // any direction.  u = x64_j is used as given; a point is counted on a
+        // side when its float64 inner product with u is on that side or within
+        // the product's error bound of it (the centring error included), so a
+        // count can only be too high and the bound stays valid.
+        int ub = 0x7fffffff;
+        if (pl.prune && p >= 2 && nnz > 0) {
+            __syncthreads();
+            const double g = ((double)p + 3.0) * kU64 * 1.01;
+            for (int j = tid; j < nnz; j += blockDim.x) {
+                double u[kMaxP];
+#pragma unroll
+                for (int c = 0; c < kMaxP; ++c) u[c] = c < p ? x64[(size_t)j * p + c] : 0.0;
+                int le = 0, ge = 0;
+                for (int i = 0; i < nnz; ++i) {
+                    double dot = 0.0, mag = 0.0;
+#pragma unroll
+                    for (int c = 0; c < kMaxP; ++c)
+                        if (c < p) {
+                            const double v = x64[(size_t)i * p + c];
+                            dot = fma(u[c], v, dot);
+                            mag = fma(fabs(u[c]), fabs(v), mag);
+                        }
+                    const double e = fma(g, mag, 0x1p-1000);
+                    // a non-finite product counts on both sides
+                    const bool fin = isfinite(dot) && isfinite(e);
+                    le += (!fin || dot <= e) ? 1 : 0;
+                    ge += (!fin || dot >= -e) ? 1 : 0;
+                }
+                ub = min(ub, min(le, ge));
+            }
+            ub = wave_min(ub);
+            __syncthreads();
+            if ((tid & 63) == 0) s_red[tid >> 6] = ub;
+            __syncthreads();
+            ub = min(min(s_red[0], s_red[1]), min(s_red[2], s_red[3]));
+            __syncthreads();
+        }
         // p = 1: closed form
         int pos1 = 0, neg1 = 0;
         if (p == 1) {
@@ -184,6 +223,7 @@ __global__ __launch_bounds__(256) void prep_kernel(Pools pl) {
             st.n0 = n - nnz;
             st.status = (bad ? kStNonfinite : 0) | (ints_ok ? 0 : kStNoExactInts);
             st.min_term = 0x7fffffff;
+            st.ub_term = ub;
             if (p == 1) st.min_term = min(pos1, neg1);
             if (nnz == 0) st.min_term = 0;
             pl.qs[q] = st;
@@ -206,7 +246,10 @@ __global__ void finalize_kernel(Pools pl) {
             st.status |= kStNoValid;
             pl.qs[q].status = st.status;
         } else {
-            out = st.n0 + st.min_term;
+            // some valid subset recorded a term; a subset skipped against the
+            // bound ub_term recorded a value at or above it, so the minimum may
+            // be the bound itself
+            out = st.n0 + min(st.min_term, st.ub_term);
         }
         *pl.qd[q].count = out;
     }

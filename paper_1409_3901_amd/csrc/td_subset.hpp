@@ -442,6 +442,10 @@ constexpr uint32_t kHistNeg = 1u << 11;
 constexpr uint32_t kHistStr = 1u << 22;
 constexpr uint32_t kAuxNeg = 1u << 31;
 constexpr int kListMax = 128;   // gathered points of the runs walked exactly
+// Key of a point that is not swept (padding, a member of I, or a point float64
+// cannot place): q - rq then lies in [2^31, 2^32), so its histogram word falls
+// in the NB words past the buckets, which the scan never reads.
+constexpr uint32_t kKeyOut = 0xffffffffu;
 
 // Buckets per lane: a quarter of the points per lane (about four points per
 // bucket).  The bounds L and U only decide when a sweep must be walked in
@@ -461,6 +465,8 @@ struct BucketGeom {
     static constexpr uint32_t W = 1u << SH;
     static constexpr double QS = (double)(NB - 2) * (double)W / 2.0;   // quanta per unit of t'
     static constexpr uint32_t RQMAX = W / 4;
+    // b = 4 eps / s below which a key radius passes the RQMAX check
+    static constexpr double BCAP = 4.0 * (double)RQMAX / QS;
 };
 
 // float64 key of a point in bucket quanta; false if not certified
@@ -490,6 +496,8 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     const int lane = lane_id();
     const float QSf = (float)G::QS;
     const float QBf = (float)(G::QS + (double)G::W);
+    // quanta per unit of b in the linear radius bound
+    const float RQS = (float)(G::QS * (1.001 / 4.0) * (1.0 + G::BCAP));
     float f1[P], f2[P];
 #pragma unroll
     for (int c = 0; c < P; ++c) {
@@ -502,7 +510,7 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     // 4 eps, eps the float32 error of each coordinate of a unit-length point
     const float eps4 = unif(4.0f * S.beta32 * fc.fscale);
     uint32_t qk[K], aux[K];
-    uint32_t weak = 0, vmask = 0;
+    uint32_t weak = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const int idx = lane * K + i;
@@ -519,9 +527,11 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
         // t' = h2 / (h1 + |h2|) + 1.  With eps the float32 error of each
         // coordinate and a = eps / s <= 1/4 (from h1 > 4 eps), the key moves by
         // at most eps / (s - 2 eps) = a / (1 - 2a) <= a + 4a^2 = (b + b^2) / 4
-        // with b = 4a; 8 u32 covers the rounding of t' (hardware reciprocal
-        // within 1 ulp) and of the scaling to quanta, 2 quanta the truncations
-        // (Algorithm 2, Step 1(b)).
+        // with b = 4a.  A radius that passes the check below has b < BCAP, so
+        // b^2 < BCAP b and the linear bound b (1 + BCAP) / 4 covers it; 8 u32
+        // covers the rounding of t' (hardware reciprocal within 1 ulp) and of
+        // the scaling to quanta, 2 quanta the truncations (Algorithm 2,
+        // Step 1(b)).
         const bool pos = y1 > 0.0f;
         const float ay1 = fabsf(y1);
         const float h2 = pos ? y2 : -y2;
@@ -529,12 +539,11 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
         const float rs = __builtin_amdgcn_rcpf(s);
         const float u = h2 * rs;
         const float b = eps4 * rs;
-        const float rqf = fmaf(fmaf(b, b, b), QSf * (1.001f / 4.0f), 8.0f * kU32 * QSf + 2.0f);
+        const float rqf = fmaf(b, RQS, 8.0f * kU32 * QSf + 2.0f);
         const bool ok = (ay1 > eps4) && (rqf < (float)(G::RQMAX - 4));
-        qk[i] = (uint32_t)fmaf(u, QSf, QBf);
+        qk[i] = valid ? (uint32_t)fmaf(u, QSf, QBf) : kKeyOut;
         aux[i] = (uint32_t)rqf | (pos ? 0u : kAuxNeg);
         weak |= (valid && !ok) ? (1u << i) : 0u;
-        vmask |= valid ? (1u << i) : 0u;
     }
     // Points that float64 cannot place either (near the fold line, or inside
     // span(x_I)) are left out of the sweep; `partial` records it.  Leaving
@@ -568,23 +577,24 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
                 qk[i] = wq[i];
                 aux[i] = (uint32_t)wa[i];
             }
-        vmask &= ~lost;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if ((lost >> i) & 1u) qk[i] = kKeyOut;
         partial = __any(lost != 0);
     }
-    // histogram, branch-free: points that are not swept add to a word of
-    // their own lane past the buckets (hist holds NB + 64 words, the extra
-    // ones are never read)
+    // histogram, branch-free: a point that is not swept (key kKeyOut) adds
+    // to one of the NB words past the buckets (hist holds 2 NB words; the
+    // extra ones are never read)
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const uint32_t rq = aux[i] & 0x7fffffffu;
         const uint32_t blo = (qk[i] - rq) >> G::SH;
         // crossing count field: 1 when the interval ends in the next bucket
         const uint32_t inc = ((aux[i] & kAuxNeg) ? kHistNeg : kHistPos) | ((((qk[i] + rq) >> G::SH) - blo) << 22);
-        const bool v = (vmask >> i) & 1u;
-        atomicAdd(&hist[v ? (blo & (NB - 1)) : (uint32_t)(NB + lane)], inc);
+        atomicAdd(&hist[blo], inc);
     }
     __syncthreads();
-    // scan of the lane's K buckets [lane K, lane K + K)
+    // scan of the lane's NBL buckets [lane NBL, lane NBL + NBL)
     uint32_t w[NBL];
 #pragma unroll
     for (int j = 0; j < NBL; ++j) w[j] = hist[lane * NBL + j];
@@ -669,7 +679,7 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
         const uint32_t blo = ((qk[i] - rq) >> G::SH) & (NB - 1);
         const uint32_t ri = hist[blo] & 0x7fffffffu;
         rinf[i] = ri;
-        const bool g = ((vmask >> i) & 1u) && (hist[(ri >> 11) & (NB - 1)] >> 31);
+        const bool g = (qk[i] != kKeyOut) && (hist[(ri >> 11) & (NB - 1)] >> 31);
         gm |= g ? (1u << i) : 0u;
         cnt += g ? 1 : 0;
     }
@@ -849,7 +859,7 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
     __shared__ Slot slots[64];
     constexpr bool BUCKET = TIER == kFiltBucket;
     __shared__ uint16_t side[TIER == kFilt ? M : 1];
-    __shared__ uint32_t hist[BUCKET ? BucketGeom<K>::NB + 64 : 1];
+    __shared__ uint32_t hist[BUCKET ? 2 * BucketGeom<K>::NB : 1];
     __shared__ uint4 glist[BUCKET ? kListMax : 1];
     // per-block device scratch: float64 basis slots, then the staging arrays
     uint8_t* wsc = pl.wscratch + pl.cp->cls_scratch[pl.cls] + (uint64_t)blockIdx.x * pl.wscratch_bytes;
@@ -867,7 +877,6 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
     if constexpr (BUCKET) {
 #pragma unroll
         for (int j = 0; j < BucketGeom<K>::NBL; ++j) hist[lane * BucketGeom<K>::NBL + j] = 0u;
-        hist[BucketGeom<K>::NB + lane] = 0u;
         __syncthreads();
     }
     double xd[TIER == kPlain ? K : 1][P];
@@ -897,11 +906,20 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
         fc.nrm = pl.nrm + d.n_off;
         fc.idx_bits = d.idx_bits;
         int wbest = kBig;
-        // running minimum of the query (terms of other work items so far)
         int qbest = kBig;
-        if constexpr (BUCKET)
-            qbest = uni(__hip_atomic_load(&pl.qs[q].min_term, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         for (uint64_t rb = r0; rb < r1; rb += 64) {
+            if constexpr (TIER != kPlain) {
+                // running minimum of the query (terms of other work items so
+                // far) and, for the bucketed sweep, the bound from the
+                // directions +-x_j; refreshed for every batch of 64 subsets
+                qbest = uni(__hip_atomic_load(&pl.qs[q].min_term, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                // a term of 0 cannot be lowered: the rest of the item is not needed
+                if (pl.prune && min(qbest, wbest) == 0) {
+                    if (lane == 0) atomicAdd(&pl.ctr->pruned, (unsigned long long)(r1 - rb));
+                    break;
+                }
+                if constexpr (BUCKET) qbest = min(qbest, uni(st.ub_term));
+            }
             const uint64_t myr = rb + (uint64_t)lane;
             Slot& my = slots[lane];
             if (myr < r1) {
@@ -1009,8 +1027,12 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
                     ++ndefer;
                     continue;
                 }
-                if (term == kSkip) {   // bounded below by a term already reached
+                if (term == kSkip) {
+                    // bounded below by a term already reached or by ub_term:
+                    // the subset is valid (certified basis) and its term is at
+                    // least that bound, which it records
                     ++swept;
+                    wbest = min(wbest, qbest);
                     continue;
                 }
                 ++swept;

@@ -37,7 +37,7 @@ def test_struct_layouts_match_header():
     # sizeof(td_options), sizeof(td_problem), sizeof(td_stats) on x86-64
     assert ctypes.sizeof(td.Options) == 48
     assert ctypes.sizeof(td.Problem) == 48
-    assert ctypes.sizeof(td.Stats) == 80
+    assert ctypes.sizeof(td.Stats) == 88
 
 
 def test_status_strings_and_version(lib):
@@ -50,7 +50,7 @@ def test_invalid_arguments_rejected_without_device(lib):
     import paper_1409_3901_amd as td
     o = td.Options()
     assert lib.td_default_options(ctypes.byref(o)) == 0
-    assert o.precision == 1 and o.filter_scale == 1.0
+    assert o.precision == 1 and o.filter_scale == 1.0 and o.prune == 1 and o.sweep == 0
     nul = ctypes.c_void_p(0)
     fake = ctypes.c_void_p(0x1000)
     # null pointers
@@ -73,6 +73,12 @@ def test_invalid_arguments_rejected_without_device(lib):
     assert lib.td_depth_ex(fake, 10, 3, fake, 2, fake, ctypes.byref(bad), nul) == 1
     bad.filter_scale = 1.0
     bad.precision = 7
+    assert lib.td_depth_ex(fake, 10, 3, fake, 2, fake, ctypes.byref(bad), nul) == 1
+    bad.precision = 1
+    bad.sweep = 2
+    assert lib.td_depth_ex(fake, 10, 3, fake, 2, fake, ctypes.byref(bad), nul) == 1
+    bad.sweep = 0
+    bad.prune = 2
     assert lib.td_depth_ex(fake, 10, 3, fake, 2, fake, ctypes.byref(bad), nul) == 1
     # batched: null array / negative count
     assert lib.td_depth_batched(None, 1, None, nul) == 1
