@@ -484,6 +484,66 @@ __device__ __forceinline__ bool bucket_key64(double d1, double d2, double eps64,
     return true;
 }
 
+// Float32 key of one point for the bucketed sweep: projection on (e1, e2),
+// fold by the sign of the first coordinate, pseudo-angle
+// t' = h2 / (h1 + |h2|) + 1 in bucket quanta, and its radius.  With eps the
+// float32 error of each coordinate and a = eps / s <= 1/4 (from h1 > 4 eps),
+// the key moves by at most eps / (s - 2 eps) = a / (1 - 2a) <= a + 4a^2 =
+// (b + b^2) / 4 with b = 4a.  A radius that passes the check has b < BCAP, so
+// b^2 < BCAP b and the linear bound b (1 + BCAP) / 4 covers it; 8 u32 covers
+// the rounding of t' (hardware reciprocal within 1 ulp) and of the scaling to
+// quanta, 2 quanta the truncations (Algorithm 2, Step 1(b)).  Returns whether
+// the fold and the key are certified.  Contraction is off, so every
+// evaluation of a point gives the same bits.
+template <int P, int K>
+__device__ __forceinline__ bool key32(const float (&x)[P], const float (&f1)[P], const float (&f2)[P], float eps4,
+                                      float eR, uint32_t& q, uint32_t& rq, bool& pos) {
+#pragma clang fp contract(off)
+    using G = BucketGeom<K>;
+    const float QSf = (float)G::QS;
+    const float QBf = (float)(G::QS + (double)G::W);
+    float y1 = 0.0f, y2 = 0.0f;
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        y1 = fmaf(f1[c], x[c], y1);
+        y2 = fmaf(f2[c], x[c], y2);
+    }
+    pos = y1 > 0.0f;
+    const float ay1 = fabsf(y1);
+    const float h2 = pos ? y2 : -y2;
+    const float s = ay1 + fabsf(h2);
+    const float rs = __builtin_amdgcn_rcpf(s);
+    const float u = h2 * rs;
+    // b RQS with b = eps4 / s, as rs (eps4 RQS)
+    const float rqf = fmaf(rs, eR, 8.0f * kU32 * QSf + 2.0f);
+    q = (uint32_t)fmaf(u, QSf, QBf);
+    rq = (uint32_t)rqf;   // meaningful only when the key is certified
+    return (ay1 > eps4) && (rqf < (float)(G::RQMAX - 4));
+}
+
+// Histogram add of a float32 key that may be uncertified (ok false): such a
+// point takes the lane's own word past the buckets (hist holds 2 NB words;
+// the extra ones are never read).
+template <int K>
+__device__ __forceinline__ void hist_add32(uint32_t* hist, uint32_t q, uint32_t rq, bool pos, bool ok, uint32_t out_lo) {
+    using G = BucketGeom<K>;
+    const uint32_t lo = ok ? q - rq : out_lo;
+    const uint32_t blo = lo >> G::SH;
+    const uint32_t inc = (pos ? kHistPos : kHistNeg) | ((((q + rq) >> G::SH) - blo) << 22);
+    atomicAdd(&hist[blo], inc);
+}
+
+// Histogram add of a key from the float64 re-check: a point that is not
+// swept (key kKeyOut) adds to one of the NB words past the buckets.
+template <int K>
+__device__ __forceinline__ void hist_add(uint32_t* hist, uint32_t q, uint32_t rq, bool pos) {
+    using G = BucketGeom<K>;
+    const uint32_t blo = (q - rq) >> G::SH;
+    // crossing count field: 1 when the interval ends in the next bucket
+    const uint32_t inc = (pos ? kHistPos : kHistNeg) | ((((q + rq) >> G::SH) - blo) << 22);
+    atomicAdd(&hist[blo], inc);
+}
+
 template <int P, int K>
 __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
                             const SlotF64<P>& S64, int nnz, const FiltCtx& fc, uint32_t* hist, uint4* list,
@@ -494,10 +554,6 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     constexpr int NB = G::NB;
     constexpr int NBL = G::NBL;
     const int lane = lane_id();
-    const float QSf = (float)G::QS;
-    const float QBf = (float)(G::QS + (double)G::W);
-    // quanta per unit of b in the linear radius bound
-    const float RQS = (float)(G::QS * (1.001 / 4.0) * (1.0 + G::BCAP));
     float f1[P], f2[P];
 #pragma unroll
     for (int c = 0; c < P; ++c) {
@@ -509,52 +565,68 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     for (int c = 0; c < KS; ++c) mem[c] = uni(S.mem[c]);
     // 4 eps, eps the float32 error of each coordinate of a unit-length point
     const float eps4 = unif(4.0f * S.beta32 * fc.fscale);
-    uint32_t qk[K], aux[K];
-    uint32_t weak = 0;
+    // eps4 times the quanta per unit of b = 4 eps / s in the linear radius bound
+    const float eR = eps4 * (float)(G::QS * (1.001 / 4.0) * (1.0 + G::BCAP));
+    // Keys and histogram in one pass; the keys are not kept: the rare walk
+    // evaluates them again.  Points float32 cannot certify are re-checked in
+    // float64 below and keep their keys in the staging arrays.
+    // The members of I lie in span(x_I): their float32 coordinates are within
+    // the error bound of 0, so they never pass the key check and are left out
+    // like every other point that fails it.
+    // Padding rows past nnz are zero and fail the key check too.  A point
+    // that fails it adds to the word 2 NB - 1 - lane, past the buckets.
+    const uint32_t out_lo = 0xffffffffu - ((uint32_t)lane << G::SH);
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        const int idx = lane * K + i;
-        bool valid = idx < nnz;
-#pragma unroll
-        for (int c = 0; c < KS; ++c) valid = valid && (idx != mem[c]);
-        float y1 = 0.0f, y2 = 0.0f;
-#pragma unroll
-        for (int c = 0; c < P; ++c) {
-            y1 = fmaf(f1[c], xr[i][c], y1);
-            y2 = fmaf(f2[c], xr[i][c], y2);
-        }
-        // Fold by the sign of the first coordinate, pseudo-angle
-        // t' = h2 / (h1 + |h2|) + 1.  With eps the float32 error of each
-        // coordinate and a = eps / s <= 1/4 (from h1 > 4 eps), the key moves by
-        // at most eps / (s - 2 eps) = a / (1 - 2a) <= a + 4a^2 = (b + b^2) / 4
-        // with b = 4a.  A radius that passes the check below has b < BCAP, so
-        // b^2 < BCAP b and the linear bound b (1 + BCAP) / 4 covers it; 8 u32
-        // covers the rounding of t' (hardware reciprocal within 1 ulp) and of
-        // the scaling to quanta, 2 quanta the truncations (Algorithm 2,
-        // Step 1(b)).
-        const bool pos = y1 > 0.0f;
-        const float ay1 = fabsf(y1);
-        const float h2 = pos ? y2 : -y2;
-        const float s = ay1 + fabsf(h2);
-        const float rs = __builtin_amdgcn_rcpf(s);
-        const float u = h2 * rs;
-        const float b = eps4 * rs;
-        const float rqf = fmaf(b, RQS, 8.0f * kU32 * QSf + 2.0f);
-        const bool ok = (ay1 > eps4) && (rqf < (float)(G::RQMAX - 4));
-        qk[i] = valid ? (uint32_t)fmaf(u, QSf, QBf) : kKeyOut;
-        aux[i] = (uint32_t)rqf | (pos ? 0u : kAuxNeg);
-        weak |= (valid && !ok) ? (1u << i) : 0u;
+        uint32_t q, rq;
+        bool pos;
+        const bool ok = key32<P, K>(xr[i], f1, f2, eps4, eR, q, rq, pos);
+        hist_add32<K>(hist, q, rq, pos, ok, out_lo);
     }
-    // Points that float64 cannot place either (near the fold line, or inside
-    // span(x_I)) are left out of the sweep; `partial` records it.  Leaving
-    // points out lowers every count, and delta_I >= 0, so the bounds of the
-    // remaining points still bound delta_I + b_I from below.
+    __syncthreads();
+    // totals of the lane's NBL buckets [lane NBL, lane NBL + NBL) and of the
+    // sweep: m points placed, S0 of them with delta = -1
+    uint32_t w[NBL];
+    uint32_t tl;
+    int incl, tot;
+    auto totals = [&]() {
+#pragma unroll
+        for (int j = 0; j < NBL; ++j) w[j] = hist[lane * NBL + j];
+        tl = 0;
+#pragma unroll
+        for (int j = 0; j < NBL; ++j) tl += w[j];
+        tl &= 0x3fffffu;   // per-field sums stay below 2^11: no carry between fields
+        incl = wave_incl_sum_dpp((int)tl);
+        tot = __builtin_amdgcn_readlane(incl, 63);
+    };
+    totals();
+    // Every point outside I and below nnz that float32 placed is counted; if
+    // fewer than nnz - |I| are, some need the float64 re-check.  Points that
+    // float64 cannot place either (near the fold line, or inside span(x_I))
+    // are left out of the sweep; `partial` records it.  Leaving points out
+    // lowers every count, and delta_I >= 0, so the bounds of the remaining
+    // points still bound delta_I + b_I from below.
     bool partial = false;
-    if (__any(weak != 0)) {
-        // float32 cannot settle the fold or the key: float64 re-check through
+    uint32_t* wq = sg.pkey + lane * K;
+    int* wa = sg.pS + lane * K;
+    uint32_t weak = 0;
+    if ((tot & 0x7ff) + ((tot >> 11) & 0x7ff) < nnz - KS) {
+        // which points: the same evaluation again (from an opaque copy of
+        // eps4, so that the compiler does not keep the first evaluation's
+        // values live instead); then a float64 re-check with the keys kept in
         // the staging arrays (rolled loop, rare path)
-        uint32_t* wq = sg.pkey + lane * K;
-        int* wa = sg.pS + lane * K;
+        float eps4r = eps4;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int idx = lane * K + i;
+            bool valid = idx < nnz;
+#pragma unroll
+            for (int c = 0; c < KS; ++c) valid = valid && (idx != mem[c]);
+            uint32_t q, rq;
+            bool pos;
+            const bool ok = key32<P, K>(xr[i], f1, f2, eps4r, eR, q, rq, pos);
+            weak |= (valid && !ok) ? (1u << i) : 0u;
+        }
         uint32_t lost = 0;
 #pragma unroll 1
         for (int i = 0; i < K; ++i) {
@@ -564,49 +636,22 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
             double d1, d2;
             fp64_point<P>(fc.x64, S64.e1, S64.e2, idx, d1, d2);
             uint32_t q2, a2;
-            if (bucket_key64<K>(d1, d2, S64.beta64 * (double)fc.nrm[idx], q2, a2)) {
-                wq[i] = q2;
-                wa[i] = (int)a2;
-            } else {
+            if (!bucket_key64<K>(d1, d2, S64.beta64 * (double)fc.nrm[idx], q2, a2)) {
+                q2 = kKeyOut;
+                a2 = 0u;
                 lost |= 1u << i;
             }
+            wq[i] = q2;
+            wa[i] = (int)a2;
+            hist_add<K>(hist, q2, a2 & 0x7fffffffu, !(a2 & kAuxNeg));
         }
-#pragma unroll
-        for (int i = 0; i < K; ++i)
-            if ((weak >> i) & 1u) {
-                qk[i] = wq[i];
-                aux[i] = (uint32_t)wa[i];
-            }
-#pragma unroll
-        for (int i = 0; i < K; ++i)
-            if ((lost >> i) & 1u) qk[i] = kKeyOut;
         partial = __any(lost != 0);
+        __syncthreads();
+        totals();
     }
-    // histogram, branch-free: a point that is not swept (key kKeyOut) adds
-    // to one of the NB words past the buckets (hist holds 2 NB words; the
-    // extra ones are never read)
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const uint32_t rq = aux[i] & 0x7fffffffu;
-        const uint32_t blo = (qk[i] - rq) >> G::SH;
-        // crossing count field: 1 when the interval ends in the next bucket
-        const uint32_t inc = ((aux[i] & kAuxNeg) ? kHistNeg : kHistPos) | ((((qk[i] + rq) >> G::SH) - blo) << 22);
-        atomicAdd(&hist[blo], inc);
-    }
-    __syncthreads();
-    // scan of the lane's NBL buckets [lane NBL, lane NBL + NBL)
-    uint32_t w[NBL];
-#pragma unroll
-    for (int j = 0; j < NBL; ++j) w[j] = hist[lane * NBL + j];
 #pragma unroll
     for (int j = 0; j < NBL; ++j) hist[lane * NBL + j] = 0u;
-    uint32_t tl = 0;
-#pragma unroll
-    for (int j = 0; j < NBL; ++j) tl += w[j];
-    tl &= 0x3fffffu;   // per-field sums stay below 2^11: no carry between fields
-    const int incl = wave_incl_sum_dpp((int)tl);
     const int pre = incl - (int)tl;
-    const int tot = __builtin_amdgcn_readlane(incl, 63);
     const int S0 = tot & 0x7ff;
     const int m = S0 + ((tot >> 11) & 0x7ff);
     const int Sst = S0 - (pre & 0x7ff) + ((pre >> 11) & 0x7ff);
@@ -626,16 +671,18 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
             s += nn - np;
         }
     }
-    U = wave_min_dpp(U);
     L = wave_min_dpp(L);
-    // With points left out, only the lower bound holds: a subset that cannot
-    // go below `ubound` (a term the query already reached) is not needed,
-    // anything else goes to the exact tier.
-    if (partial) return L >= ubound ? kSkip : kDefer;
-    // Done when L = U; also when L is not below `ubound`: then no state of
-    // this sweep can lower the minimum over subsets, and U (>= b_I >= L) is
-    // returned in place of b_I.
-    if (L >= U || L >= ubound) return U;
+    // When L is not below `ubound` (a term the query already reached, or the
+    // bound from the directions +-x_j), no state of this sweep can lower the
+    // minimum over subsets: the subset is not needed (the caller records the
+    // bound for it).  This holds with points left out too, since leaving
+    // points out only lowers the states; otherwise such a sweep goes to the
+    // exact tier.
+    if (L >= ubound) return kSkip;
+    if (partial) return kDefer;
+    // Done when L = U.
+    U = wave_min_dpp(U);
+    if (L >= U) return U;
     ++walked;
 
     // ---- rare: walk the runs whose range dips below U in exact order.
@@ -672,9 +719,26 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     __syncthreads();
     uint32_t gm = 0;
     int cnt = 0;
-    uint32_t rinf[K];
+    uint32_t qk[K], aux[K], rinf[K];
+    float eps4w = eps4;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
+        // the same keys as the histogram's: float32 again, or the float64
+        // re-check's from the staging arrays
+        if ((weak >> i) & 1u) {
+            qk[i] = wq[i];
+            aux[i] = (uint32_t)wa[i];
+        } else {
+            const int idx = lane * K + i;
+            bool valid = idx < nnz;
+#pragma unroll
+            for (int c = 0; c < KS; ++c) valid = valid && (idx != mem[c]);
+            uint32_t q, rq;
+            bool pos;
+            const bool ok = key32<P, K>(xr[i], f1, f2, eps4w, eR, q, rq, pos);
+            qk[i] = (valid && ok) ? q : kKeyOut;
+            aux[i] = (rq & 0x7fffffffu) | (pos ? 0u : kAuxNeg);
+        }
         const uint32_t rq = aux[i] & 0x7fffffffu;
         const uint32_t blo = ((qk[i] - rq) >> G::SH) & (NB - 1);
         const uint32_t ri = hist[blo] & 0x7fffffffu;
