@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--c4", action="store_true",
                     help="batched workload instead: 256 datasets in one graph launch vs "
                          "256*8 plain float64 launches")
+    ap.add_argument("--paper-grid", action="store_true",
+                    help="the paper's simulation grid (X ~ N(0, I_p), z = 0, one query), "
+                         "timed per query beside the paper's own timings as context")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -112,6 +115,8 @@ def main():
         return
     if a.c4:
         return bench_c4(a, td, workloads, torch, np, dev)
+    if a.paper_grid:
+        return bench_paper_grid(td, workloads, torch, np, dev)
     X, Z = workloads.c3()
     n, p = X.shape
     m = Z.shape[0]
@@ -227,6 +232,15 @@ def bench_c4(a, td, workloads, torch, np, dev):
             n0 = int(np.sum(np.all(X == Z[q], axis=1)))
             sweeps += math.comb(n - n0, p - 2)
     note("%d sweeps" % sweeps)
+    # launch shapes tuned per (p, sort width) class, at the class's largest n
+    classes = {}
+    for X, Z in data:
+        n, p = X.shape
+        k = max(64, 1 << (n - 1).bit_length()) // 64
+        classes[(p, k)] = max(classes.get((p, k), 0), n)
+    for (p, k), n in sorted(classes.items()):
+        td.autotune(p, n)
+    note("autotuned %d classes" % len(classes))
     td.depth_batched(probs)       # captures the graph
     torch.cuda.synchronize()
     note("warm-up launch done")
@@ -256,6 +270,44 @@ def bench_c4(a, td, workloads, torch, np, dev):
            "mismatches_batched_vs_plain": int(np.sum(got != pl)),
            "deferred_subsets": st["deferred_subsets"], "device_status": st["device_status"]}
     print(json.dumps(res), flush=True)
+
+
+# The paper's timings of its first algorithm (Table 2: seconds per query,
+# X ~ N(0, I_p), z = 0, Matlab 7.8 on an Intel Core i7-2670QM at 2.2 GHz),
+# quoted as context only: other hardware, software and data.
+PAPER_TABLE2_S = {
+    (3, 40): 0.0268, (3, 80): 0.0481, (3, 160): 0.0899, (3, 320): 0.2531, (3, 640): 0.8073,
+    (4, 40): 0.1876, (4, 80): 0.8045, (4, 160): 5.0550, (4, 320): 43.3812, (4, 640): 248.5797,
+    (5, 40): 1.9517, (5, 80): 21.1227, (5, 160): 262.3251, (5, 320): 3864.4624,
+    (6, 40): 18.4515, (6, 80): 446.0153, (6, 160): 14695.1294,
+}
+
+
+def bench_paper_grid(td, workloads, torch, np, dev):
+    """One query z = 0 on X ~ N(0, I_p) for the (p, n) points of the paper's
+    simulation table that fit the library (n <= 1024): the GPU time per query
+    (the library's own HIP events over the whole call, best of 5) beside the
+    paper's seconds per query."""
+    rows = []
+    for (p, n), paper_s in sorted(PAPER_TABLE2_S.items()):
+        X, Z = workloads.grid(p, n, 0.0)
+        Xd = torch.from_numpy(X).to(dev)
+        Zd = torch.from_numpy(Z).to(dev)
+        td.depth(Xd, Zd)
+        best = None
+        for _ in range(5):
+            c = td.depth(Xd, Zd, timing=True)
+            torch.cuda.synchronize()
+            ms = td.get_stats()["total_ms"]
+            best = ms if best is None else min(best, ms)
+        rows.append({"p": p, "n": n, "depth": int(c.cpu()[0]), "gpu_ms_per_query": best,
+                     "subsets": math.comb(n, p - 2), "paper_s_per_query": paper_s,
+                     "paper_over_gpu": paper_s * 1e3 / best})
+        print("[grid] p=%d n=%d %.3f ms" % (p, n, best), file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "seconds per query on the paper's simulation grid (context)",
+                      "unit": "ms", "n_gpus": 1, "data": "synthetic",
+                      "paper_hardware": "Intel Core i7-2670QM 2.2 GHz, Matlab 7.8 (Table 2)",
+                      "rows": rows}), flush=True)
 
 
 def cpu_baseline(X, Z, seconds):

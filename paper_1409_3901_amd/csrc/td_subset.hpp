@@ -422,7 +422,7 @@ __device__ int sweep_filt(const float (&xr)[K][P], const SlotFilt<P>& S,
 // pseudo-angle) and refined exactly only where the minimum may lie.
 //
 // Keys: t' in [0, 2] maps to q = t' QS + W - QS ... in quanta, q in
-// [W, (NB - 1) W], with NB buckets (M/4) of W = 2^31 / NB quanta.  Every point
+// [W, (NB - 1) W], with NB buckets (M/8) of W = 2^31 / NB quanta.  Every point
 // carries a certified interval [q - rq, q + rq] (rq < W / 4) that contains the
 // key of the exact frame, so a bucket boundary that no interval crosses is a
 // strict gap of the angular order, and the state there is a state of the
@@ -447,14 +447,14 @@ constexpr int kListMax = 128;   // gathered points of the runs walked exactly
 // in the NB words past the buckets, which the scan never reads.
 constexpr uint32_t kKeyOut = 0xffffffffu;
 
-// Buckets per lane: a quarter of the points per lane (about four points per
+// Buckets per lane: an eighth of the points per lane (about eight points per
 // bucket).  The bounds L and U only decide when a sweep must be walked in
 // exact order, and with the running-minimum bound that is rare, so fewer,
 // wider buckets cost little there and shorten the scan (measured on p = 5,
-// n = 500: M/4 buckets beat M/2 by a third and match M/8, which walks twice
-// as often).
+// n = 500: M/8 buckets walk twice as often as M/4 and are 2% faster; M/2
+// is 5% slower than M/4).
 template <int K>
-constexpr int buckets_per_lane() { return K >= 4 ? K / 4 : 1; }
+constexpr int buckets_per_lane() { return K >= 8 ? K / 8 : 1; }
 
 template <int K>
 struct BucketGeom {
@@ -554,15 +554,14 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     constexpr int NB = G::NB;
     constexpr int NBL = G::NBL;
     const int lane = lane_id();
+    // basis rows as read from LDS (every lane reads the same words), kept in
+    // vector registers: no lane-to-scalar moves per sweep
     float f1[P], f2[P];
 #pragma unroll
     for (int c = 0; c < P; ++c) {
-        f1[c] = unif(S.f1[c]);
-        f2[c] = unif(S.f2[c]);
+        f1[c] = S.f1[c];
+        f2[c] = S.f2[c];
     }
-    int mem[KS > 0 ? KS : 1];
-#pragma unroll
-    for (int c = 0; c < KS; ++c) mem[c] = uni(S.mem[c]);
     // 4 eps, eps the float32 error of each coordinate of a unit-length point
     const float eps4 = unif(4.0f * S.beta32 * fc.fscale);
     // eps4 times the quanta per unit of b = 4 eps / s in the linear radius bound
@@ -616,6 +615,9 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
         // values live instead); then a float64 re-check with the keys kept in
         // the staging arrays (rolled loop, rare path)
         float eps4r = eps4;
+        int mem[KS > 0 ? KS : 1];
+#pragma unroll
+        for (int c = 0; c < KS; ++c) mem[c] = uni(S.mem[c]);
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             const int idx = lane * K + i;
@@ -720,6 +722,9 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     uint32_t gm = 0;
     int cnt = 0;
     uint32_t qk[K], aux[K], rinf[K];
+    int mem[KS > 0 ? KS : 1];
+#pragma unroll
+    for (int c = 0; c < KS; ++c) mem[c] = uni(S.mem[c]);
     float eps4w = eps4;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
