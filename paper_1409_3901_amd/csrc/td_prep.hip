@@ -27,6 +27,7 @@ __global__ void init_kernel(Counters* ctr) {
 __global__ __launch_bounds__(256) void prep_kernel(Pools pl) {
     __shared__ int s_flag[kMaxN];
     __shared__ int s_pos[kMaxN];
+    __shared__ float s_x[kMaxN * kMaxP];
     __shared__ int s_red[8];
     __shared__ int s_q;
     __shared__ double s_z[kMaxP];
@@ -162,33 +163,31 @@ __global__ __launch_bounds__(256) void prep_kernel(Pools pl) {
         }
         // Upper bound of the minimum from the 2n' directions +-x_j (Algorithm
         // 3, Step 2(a)): the depth is at most the closed halfspace count of
-        // any direction.  u = x64_j is used as given; a point is counted on a
-        // side when its float64 inner product with u is on that side or within
-        // the product's error bound of it (the centring error included), so a
-        // count can only be too high and the bound stays valid.
+        // any direction.  The directions are the float32 unit copies u = x32_j
+        // (any direction gives a valid bound), and the signs are those of
+        // <u, x32_i>: x32_i is x_i / ||x_i|| up to u32 per coordinate, both
+        // vectors have norm at most 1 + p u32, so the float32 inner product
+        // is within e = (p + 4) u32 of the sign-deciding <u, x_i / ||x_i||>.
+        // A point within e of a side is counted on it, so a count can only be
+        // too high and the bound stays valid.
         int ub = 0x7fffffff;
         if (pl.prune && p >= 2 && nnz > 0) {
             __syncthreads();
-            const double g = ((double)p + 3.0) * kU64 * 1.01;
+            for (int k = tid; k < nnz * p; k += blockDim.x) s_x[k] = x32[k];
+            __syncthreads();
+            const float e = ((float)p + 4.0f) * kU32;
             for (int j = tid; j < nnz; j += blockDim.x) {
-                double u[kMaxP];
+                float u[kMaxP];
 #pragma unroll
-                for (int c = 0; c < kMaxP; ++c) u[c] = c < p ? x64[(size_t)j * p + c] : 0.0;
+                for (int c = 0; c < kMaxP; ++c) u[c] = c < p ? s_x[j * p + c] : 0.0f;
                 int le = 0, ge = 0;
                 for (int i = 0; i < nnz; ++i) {
-                    double dot = 0.0, mag = 0.0;
+                    float dot = 0.0f;
 #pragma unroll
                     for (int c = 0; c < kMaxP; ++c)
-                        if (c < p) {
-                            const double v = x64[(size_t)i * p + c];
-                            dot = fma(u[c], v, dot);
-                            mag = fma(fabs(u[c]), fabs(v), mag);
-                        }
-                    const double e = fma(g, mag, 0x1p-1000);
-                    // a non-finite product counts on both sides
-                    const bool fin = isfinite(dot) && isfinite(e);
-                    le += (!fin || dot <= e) ? 1 : 0;
-                    ge += (!fin || dot >= -e) ? 1 : 0;
+                        if (c < p) dot = fmaf(u[c], s_x[i * p + c], dot);
+                    le += dot <= e ? 1 : 0;
+                    ge += dot >= -e ? 1 : 0;
                 }
                 ub = min(ub, min(le, ge));
             }

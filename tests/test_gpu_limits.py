@@ -1,0 +1,55 @@
+"""The edges of the supported range against the oracle: the largest
+dimensions (p = 7, 8, where a subset has 5 or 6 members and the sort classes
+run at one or two waves per SIMD) and the largest sample (n = 1024, the full
+sort width, where p = 2 puts 1024 points in one sweep, more than the bucket
+words count, so every sweep goes to the exact tier)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from conftest import PREC_OPTS, to_dev
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["filtered", "bitonic", "plain"]
+
+
+def run(td, dev, X, Z, **kw):
+    c = td.depth(to_dev(X, dev), to_dev(np.atleast_2d(Z), dev), **kw)
+    return c.cpu().numpy().astype(np.int64)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("p,n", [(7, 8), (7, 13), (7, 20), (8, 9), (8, 14), (8, 17)])
+def test_largest_dimensions(td, dev, prec, p, n):
+    rng = np.random.default_rng(40 + 3 * p + n)
+    X = rng.standard_normal((n, p))
+    Z = np.vstack([rng.standard_normal((2, p)), X[:1], 4.0 * rng.standard_normal((1, p))])
+    exp = oracle.depth_counts(X, Z)
+    got = run(td, dev, X, Z, **PREC_OPTS[prec])
+    assert np.array_equal(got, exp), (got, exp)
+
+
+@pytest.mark.parametrize("prec", ["filtered", "bitonic"])
+@pytest.mark.parametrize("p", [7, 8])
+def test_largest_dimensions_lattice(td, dev, prec, p):
+    """Exact ties and points inside span(x_I) at the largest dimensions."""
+    rng = np.random.default_rng(70 + p)
+    X, Z = workloads.lattice_small(rng, p, 12, R=1)
+    exp = oracle.depth_counts(X, Z)
+    got = run(td, dev, X, Z, **PREC_OPTS[prec])
+    assert np.array_equal(got, exp), (got, exp)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("p", [2, 3])
+def test_largest_sample(td, dev, prec, p):
+    rng = np.random.default_rng(90 + p)
+    X = rng.standard_normal((1024, p))
+    Z = np.vstack([rng.standard_normal((2, p)), X[5:6], 3.0 * rng.standard_normal((1, p))])
+    exp = oracle.depth_counts(X, Z)
+    got = run(td, dev, X, Z, **PREC_OPTS[prec])
+    st = td.get_stats()
+    assert st["device_status"] == 0
+    assert np.array_equal(got, exp), (got, exp)
