@@ -325,10 +325,33 @@ def cpu_baseline(X, Z, seconds):
     t = time.time()
     _, swept = oracle.depth_range(X, z, 0, R, threads=threads)
     dt = time.time() - t
-    return {"value": swept / dt, "unit": "sweeps/s", "cores": threads, "kind": "oracle",
-            "sample": "c3 query 16, subsets of lexicographic rank [0, %d) of %d (%.1f s)"
-                      % (R, math.comb(X.shape[0], X.shape[1] - 2), dt),
-            "queries_per_s": (swept / dt) / math.comb(X.shape[0], X.shape[1] - 2)}
+    res = {"value": swept / dt, "unit": "sweeps/s", "cores": threads, "kind": "oracle",
+           "sample": "c3 query 16, subsets of lexicographic rank [0, %d) of %d (%.1f s)"
+                     % (R, math.comb(X.shape[0], X.shape[1] - 2), dt),
+           "queries_per_s": (swept / dt) / math.comb(X.shape[0], X.shape[1] - 2)}
+    res["per_core"] = [per_core_rate("c3 query 16", X, z, 3.0)]
+    import workloads
+    _, _, info = workloads.c5(return_premap=True)
+    X5 = info["X0"].astype("float64")
+    res["per_core"].append(per_core_rate("c5 query 0 (pre-map lattice, same counts)", X5,
+                                         info["Z0"][0].astype("float64"), 3.0))
+    return res
+
+
+def per_core_rate(name, X, z, seconds):
+    """The oracle on one thread over a bounded rank range of one query."""
+    import oracle
+    r = 2000
+    t = time.time()
+    oracle.depth_range(X, z, 0, r, threads=1)
+    dt = max(time.time() - t, 1e-3)
+    total = math.comb(X.shape[0], X.shape[1] - 2)
+    R = int(min(total, max(r, r * seconds / dt)))
+    t = time.time()
+    _, swept = oracle.depth_range(X, z, 0, R, threads=1)
+    dt = time.time() - t
+    return {"value": swept / dt, "unit": "sweeps/s", "cores": 1,
+            "sample": "%s, subsets of lexicographic rank [0, %d) of %d (%.1f s)" % (name, R, total, dt)}
 
 
 if __name__ == "__main__":
