@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--c4", action="store_true",
                     help="batched workload instead: 256 datasets in one graph launch vs "
                          "256*8 plain float64 launches")
+    ap.add_argument("--all-configs", action="store_true",
+                    help="every workload against its stored oracle counts: mismatches, "
+                         "fallback rates and time of the filtered and plain tiers")
     ap.add_argument("--paper-grid", action="store_true",
                     help="the paper's simulation grid (X ~ N(0, I_p), z = 0, one query), "
                          "timed per query beside the paper's own timings as context")
@@ -117,6 +120,8 @@ def main():
         return bench_c4(a, td, workloads, torch, np, dev)
     if a.paper_grid:
         return bench_paper_grid(td, workloads, torch, np, dev)
+    if a.all_configs:
+        return bench_all_configs(td, workloads, torch, np, dev)
     X, Z = workloads.c3()
     n, p = X.shape
     m = Z.shape[0]
@@ -270,6 +275,65 @@ def bench_c4(a, td, workloads, torch, np, dev):
            "mismatches_batched_vs_plain": int(np.sum(got != pl)),
            "deferred_subsets": st["deferred_subsets"], "device_status": st["device_status"]}
     print(json.dumps(res), flush=True)
+
+
+def _stored_counts(cfg):
+    """Stored oracle counts of a workload (tests/golden, merged over parts)."""
+    import glob
+    gold = os.path.join(ROOT, "tests", "golden")
+    counts = {}
+    for path in sorted(glob.glob(os.path.join(gold, cfg + ".json")) +
+                       glob.glob(os.path.join(gold, cfg + ".*.json"))):
+        with open(path) as f:
+            counts.update(json.load(f)["counts"])
+    return counts
+
+
+def bench_all_configs(td, workloads, torch, np, dev):
+    """Each workload through the filtered tier (bucketed sweep) and the plain
+    float64 tier, against the stored oracle counts: mismatches (0 required of
+    the filtered tier; the plain tier's are reported), float64 re-checks and
+    deferred subsets per sweep, and the HIP-event time of the call."""
+    out = {}
+
+    def one(name, X, Z, idx, exp, **opts):
+        Xd = torch.from_numpy(X).to(dev)
+        Zd = torch.from_numpy(np.ascontiguousarray(Z[idx])).to(dev)
+        td.depth(Xd, Zd, **opts)
+        c = td.depth(Xd, Zd, timing=True, **opts)
+        torch.cuda.synchronize()
+        st = td.get_stats()
+        got = c.cpu().numpy()
+        sweeps = max(st["subsets_swept"] + st["deferred_subsets"] + st["pruned_subsets"], 1)
+        return {"queries": len(idx), "mismatches": int(np.sum(got != exp)), "ms": st["total_ms"],
+                "fp64_rechecks_per_sweep": st["fp64_rechecks"] / sweeps,
+                "deferred_subsets": st["deferred_subsets"], "exact_predicates": st["exact_predicates"],
+                "pruned_subsets": st["pruned_subsets"], "device_status": st["device_status"]}
+
+    for cfg in ("c1", "c2", "c3", "c5"):
+        X, Z = workloads.config(cfg)
+        g = _stored_counts(cfg)
+        idx = sorted(int(k) for k in g)
+        exp = np.array([g[str(q)] for q in idx])
+        out[cfg] = {"filtered": one(cfg, X, Z, idx, exp),
+                    "plain": one(cfg, X, Z, idx, exp, precision="plain")}
+        print("[configs] %s done" % cfg, file=sys.stderr, flush=True)
+    # c4: the stored subsample (queries of the datasets the oracle affords)
+    data = workloads.c4()
+    g = _stored_counts("c4")
+    probs, exp = [], []
+    for d, (X, Z) in enumerate(data):
+        qs = [q for q in range(Z.shape[0]) if "%d:%d" % (d, q) in g]
+        if qs:
+            probs.append((torch.from_numpy(X).to(dev), torch.from_numpy(np.ascontiguousarray(Z[qs])).to(dev)))
+            exp.extend(g["%d:%d" % (d, q)] for q in qs)
+    outs = td.depth_batched(probs)
+    torch.cuda.synchronize()
+    got = np.concatenate([o.cpu().numpy() for o in outs])
+    out["c4_subsample"] = {"filtered_batched": {"queries": len(exp),
+                                                "mismatches": int(np.sum(got != np.array(exp)))}}
+    print(json.dumps({"metric": "mismatches against the oracle and fallback rates, every workload",
+                      "n_gpus": 1, "data": "synthetic", "configs": out}), flush=True)
 
 
 # The paper's timings of its first algorithm (Table 2: seconds per query,
