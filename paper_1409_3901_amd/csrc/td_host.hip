@@ -26,6 +26,9 @@ extern "C" hipError_t td_launch_finalize(const td::Pools* pl, int blocks, hipStr
 extern "C" hipError_t td_launch_subset_plain(int P, int K, int blocks, hipStream_t s, const td::Pools* pl);
 extern "C" hipError_t td_launch_subset_filt(int P, int K, int blocks, hipStream_t s, const td::Pools* pl);
 extern "C" hipError_t td_launch_subset_bucket(int P, int K, int blocks, hipStream_t s, const td::Pools* pl);
+extern "C" int td_resident_blocks_plain(int P, int K);
+extern "C" int td_resident_blocks_filt(int P, int K);
+extern "C" int td_resident_blocks_bucket(int P, int K);
 extern "C" hipError_t td_launch_exact(int P, int K, int blocks, hipStream_t s, const td::Pools* pl, int all_items);
 extern "C" uint64_t td_exact_scratch_bytes(int P);
 
@@ -110,6 +113,7 @@ struct DeviceCtx {
     int num_cu = 256;
     std::map<hipStream_t, Workspace*> ws;
     std::map<std::string, Shape> tuned;   // (tier, p, K) -> shape
+    std::map<std::string, int> resident;  // (tier, p, K) -> blocks per CU
 };
 
 struct LastCall {
@@ -254,6 +258,20 @@ std::string tune_key(int tier, int p, int K) {
     return std::to_string(tier) + ":" + std::to_string(p) + ":" + std::to_string(K);
 }
 
+// Blocks of a subset kernel one compute unit holds (queried once per
+// device and shape; at least 1).
+int resident_blocks(DeviceCtx* dc, int tier, int p, int K) {
+    const std::string key = tune_key(tier, p, K);
+    auto it = dc->resident.find(key);
+    if (it != dc->resident.end()) return it->second;
+    int n = tier == 0 ? td_resident_blocks_plain(p, K)
+            : tier == 1 ? td_resident_blocks_filt(p, K)
+                        : td_resident_blocks_bucket(p, K);
+    n = std::max(1, std::min(n, 32));
+    dc->resident[key] = n;
+    return n;
+}
+
 struct ClassPlan {
     int p = 0, K = 0, M = 0;
     Shape shape;
@@ -359,7 +377,8 @@ td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_optio
     plan->points = pts;
     uint64_t soff = 0;
     for (ClassPlan& cp : plan->cls) {
-        int blocks = cp.shape.blocks > 0 ? cp.shape.blocks : dc->num_cu * 8;
+        // default: every compute unit filled to the kernel's occupancy
+        int blocks = cp.shape.blocks > 0 ? cp.shape.blocks : dc->num_cu * resident_blocks(dc, tier, cp.p, cp.K);
         if ((uint64_t)blocks > cp.items) blocks = (int)std::max<uint64_t>(1, cp.items);
         cp.shape.blocks = blocks;
         cp.xblocks = dc->num_cu * 4;

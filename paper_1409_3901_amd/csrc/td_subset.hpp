@@ -422,7 +422,9 @@ __device__ int sweep_filt(const float (&xr)[K][P], const SlotFilt<P>& S,
 // pseudo-angle) and refined exactly only where the minimum may lie.
 //
 // Keys: t' in [0, 2] maps to q = t' QS + W - QS ... in quanta, q in
-// [W, (NB - 1) W], with NB buckets (M/8) of W = 2^31 / NB quanta.  Every point
+// [W, (NB - 1) W], with NB buckets (M/8) of W = 2^SH quanta, SH = 24 while
+// NB W stays within 2^31 (a bucket index is then the top byte of a key, one
+// byte-select instruction), else 31 - log2 NB.  Every point
 // carries a certified interval [q - rq, q + rq] (rq < W / 4) that contains the
 // key of the exact frame, so a bucket boundary that no interval crosses is a
 // strict gap of the angular order, and the state there is a state of the
@@ -444,7 +446,8 @@ constexpr uint32_t kAuxNeg = 1u << 31;
 constexpr int kListMax = 128;   // gathered points of the runs walked exactly
 // Key of a point that is not swept (padding, a member of I, or a point float64
 // cannot place): q - rq then lies in [2^31, 2^32), so its histogram word falls
-// in the NB words past the buckets, which the scan never reads.
+// past the NB buckets (the histogram holds 2^(32 - SH) words, and the scan
+// reads only the first NB).
 constexpr uint32_t kKeyOut = 0xffffffffu;
 
 // Buckets per lane: an eighth of the points per lane (about eight points per
@@ -461,12 +464,15 @@ struct BucketGeom {
     static constexpr int NBL = buckets_per_lane<K>();
     static constexpr int NB = 64 * NBL;
     static constexpr int LOGNB = 6 + (NBL >= 2) + (NBL >= 4) + (NBL >= 8) + (NBL >= 16);
-    static constexpr int SH = 31 - LOGNB;
+    static constexpr int SH = LOGNB <= 7 ? 24 : 31 - LOGNB;
+    static constexpr int HW = 1 << (32 - SH);   // histogram words
     static constexpr uint32_t W = 1u << SH;
     static constexpr double QS = (double)(NB - 2) * (double)W / 2.0;   // quanta per unit of t'
     static constexpr uint32_t RQMAX = W / 4;
     // b = 4 eps / s below which a key radius passes the RQMAX check
     static constexpr double BCAP = 4.0 * (double)RQMAX / QS;
+    static_assert((uint64_t)NB * W <= (1ull << 31), "keys and radii stay below 2^31");
+    static_assert(HW >= NB + 64, "a word per lane past the buckets");
 };
 
 // float64 key of a point in bucket quanta; false if not certified
@@ -522,8 +528,8 @@ __device__ __forceinline__ bool key32(const float (&x)[P], const float (&f1)[P],
 }
 
 // Histogram add of a float32 key that may be uncertified (ok false): such a
-// point takes the lane's own word past the buckets (hist holds 2 NB words;
-// the extra ones are never read).
+// point takes the lane's own word past the buckets (the words past NB are
+// never read).
 template <int K>
 __device__ __forceinline__ void hist_add32(uint32_t* hist, uint32_t q, uint32_t rq, bool pos, bool ok, uint32_t out_lo) {
     using G = BucketGeom<K>;
@@ -573,7 +579,7 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     // the error bound of 0, so they never pass the key check and are left out
     // like every other point that fails it.
     // Padding rows past nnz are zero and fail the key check too.  A point
-    // that fails it adds to the word 2 NB - 1 - lane, past the buckets.
+    // that fails it adds to the word HW - 1 - lane, past the buckets.
     const uint32_t out_lo = 0xffffffffu - ((uint32_t)lane << G::SH);
 #pragma unroll
     for (int i = 0; i < K; ++i) {
@@ -673,15 +679,16 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
             s += nn - np;
         }
     }
-    L = wave_min_dpp(L);
     // When L is not below `ubound` (a term the query already reached, or the
     // bound from the directions +-x_j), no state of this sweep can lower the
     // minimum over subsets: the subset is not needed (the caller records the
     // bound for it).  This holds with points left out too, since leaving
     // points out only lowers the states; otherwise such a sweep goes to the
-    // exact tier.
-    if (L >= ubound) return kSkip;
+    // exact tier.  Every lane's bound reaching `ubound` is a wave vote; the
+    // minimum itself is reduced only when it is needed.
+    if (__all(L >= ubound)) return kSkip;
     if (partial) return kDefer;
+    L = wave_min_dpp(L);
     // Done when L = U.
     U = wave_min_dpp(U);
     if (L >= U) return U;
@@ -909,12 +916,15 @@ __device__ __forceinline__ void push_deferred(const Pools& pl, int q, uint64_t r
 
 // Waves per SIMD the register allocator is asked to fit for the bucketed
 // sweep (more resident waves hide the LDS and DPP latencies of the sweep);
-// chosen per instantiation so that no register spills land in the sweep.
+// chosen per instantiation so that no register spills land in the common
+// path of the sweep (spills in the per-batch set-up and on the rare paths
+// are accepted: at p <= 5, K = 8, four waves measured 7% faster than three).
 template <int P, int K, int TIER>
 constexpr int min_waves() {
     if (TIER != kFiltBucket) return 1;
     if (K <= 8) {
-        if (P <= 5 || (P == 6 && K <= 4)) return 3;
+        if (P <= 5) return 4;
+        if (P == 6 && K <= 4) return 3;
         return P <= 7 ? 2 : 1;
     }
     return P <= 6 ? 2 : 1;
@@ -928,7 +938,7 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
     __shared__ Slot slots[64];
     constexpr bool BUCKET = TIER == kFiltBucket;
     __shared__ uint16_t side[TIER == kFilt ? M : 1];
-    __shared__ uint32_t hist[BUCKET ? 2 * BucketGeom<K>::NB : 1];
+    __shared__ uint32_t hist[BUCKET ? BucketGeom<K>::HW : 1];
     __shared__ uint4 glist[BUCKET ? kListMax : 1];
     // per-block device scratch: float64 basis slots, then the staging arrays
     uint8_t* wsc = pl.wscratch + pl.cp->cls_scratch[pl.cls] + (uint64_t)blockIdx.x * pl.wscratch_bytes;

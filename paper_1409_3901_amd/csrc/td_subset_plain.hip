@@ -31,6 +31,15 @@ KernelFn pick(int P, int K) {
 }
 }  // namespace
 
+// Blocks of the (P, K) kernel that one compute unit holds at once (0 when
+// the shape has no kernel or the query fails).
+extern "C" int td_resident_blocks_plain(int P, int K) {
+    KernelFn f = pick(P, K);
+    int n = 0;
+    if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64, 0) != hipSuccess) return 0;
+    return n;
+}
+
 extern "C" hipError_t td_launch_subset_plain(int P, int K, int blocks, hipStream_t s, const td::Pools* pl) {
     KernelFn f = pick(P, K);
     if (!f) return hipErrorInvalidValue;
