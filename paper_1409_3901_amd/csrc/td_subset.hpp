@@ -918,7 +918,10 @@ __device__ __forceinline__ void push_deferred(const Pools& pl, int q, uint64_t r
 // sweep (more resident waves hide the LDS and DPP latencies of the sweep);
 // chosen per instantiation so that no register spills land in the common
 // path of the sweep (spills in the per-batch set-up and on the rare paths
-// are accepted: at p <= 5, K = 8, four waves measured 7% faster than three).
+// are accepted: at p <= 5, K = 8, four waves measured 7% faster than three
+// and five 30% slower; at p <= 5, K = 16, three waves measured 11% faster than
+// two on the batched workload although spills reach the sweep, and four
+// twice as slow).
 template <int P, int K, int TIER>
 constexpr int min_waves() {
     if (TIER != kFiltBucket) return 1;
@@ -927,6 +930,7 @@ constexpr int min_waves() {
         if (P == 6 && K <= 4) return 3;
         return P <= 7 ? 2 : 1;
     }
+    if (P <= 5) return 3;
     return P <= 6 ? 2 : 1;
 }
 
