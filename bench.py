@@ -197,13 +197,21 @@ def main():
         res["mismatches_vs_oracle"] = int(sum(int(counts[q]) != g[str(q)] for q in qs))
         res["queries_checked"] = len(qs)
     # roofline of the subset kernel: algorithmic ops over its event duration
-    achieved = ops / (sub_ms / 1e3) / 1e12
+    # subsets skipped by the pruning bound are not processed: their work is
+    # taken out at the largest per-sweep count of any query (a lower bound on
+    # the work done)
+    res["pruned_subsets"] = st["pruned_subsets"]
+    res["processed_sweeps_per_s"] = (sweeps - st["pruned_subsets"]) / (ms / 1e3)
+    max_ops = max(algorithmic_ops(n - n0[q] - (p - 2), p) for q in range(m))
+    ops_done = ops - st["pruned_subsets"] * max_ops
+    achieved = ops_done / (sub_ms / 1e3) / 1e12
     res["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS,
                        "unit": "TOP/s", "frac": achieved / PEAK_VALU_TOPS,
                        "traffic": profiled_traffic() if a.precision == "filtered" else None,
                        "kernel": "subset_kernel<5,8,%d>" % {"plain": 0, "bitonic": 1, "filtered": 3}[a.precision],
                        "kernel_ms": sub_ms,
-                       "ops_per_launch": ops}
+                       "ops_per_launch": ops_done,
+                       "subsets_processed": sweeps - st["pruned_subsets"]}
     if not a.no_plain and a.precision == "filtered":
         bms, bsub, bst, bcounts = timed("bitonic")
         res["filtered_bitonic"] = {"sweeps_per_s": sweeps / (bms / 1e3), "ms_per_step": bms,
