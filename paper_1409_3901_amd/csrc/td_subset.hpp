@@ -779,20 +779,30 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
             }
     }
     __syncthreads();
+    // Order the gathered points by key (runs are separated by strict gaps, so
+    // the key order keeps every run contiguous and in order): every lane
+    // ranks its two entries against the whole list, equal keys by gathering
+    // position, and writes them to their ranks.
+    {
+        static_assert(kListMax <= 128, "two list entries per lane");
+        const int j0 = lane, j1 = lane + 64;
+        uint4 v0 = make_uint4(0u, 0u, 0u, 0u), v1 = v0;
+        if (j0 < gtot) v0 = list[j0];
+        if (j1 < gtot) v1 = list[j1];
+        int r0 = 0, r1 = 0;
+#pragma unroll 4
+        for (int u = 0; u < gtot; ++u) {
+            const uint32_t ku = list[u].x;
+            r0 += (ku < v0.x || (ku == v0.x && u < j0)) ? 1 : 0;
+            r1 += (ku < v1.x || (ku == v1.x && u < j1)) ? 1 : 0;
+        }
+        __syncthreads();
+        if (j0 < gtot) list[r0] = v0;
+        if (j1 < gtot) list[r1] = v1;
+        __syncthreads();
+    }
     int best = kBig, defer = 0;
     if (lane == 0) {
-        // insertion sort by key (runs are separated by strict gaps, so the
-        // key order keeps every run contiguous and in order)
-#pragma unroll 1
-        for (int a = 1; a < gtot; ++a) {
-            const uint4 v = list[a];
-            int b = a;
-            while (b > 0 && list[b - 1].x > v.x) {
-                list[b] = list[b - 1];
-                --b;
-            }
-            list[b] = v;
-        }
         int k = 0;
 #pragma unroll 1
         while (k < gtot && !defer) {

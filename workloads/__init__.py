@@ -29,6 +29,14 @@ headline configurations of this project):
            30% of centred coordinates exceed 2^24, so float32 rounding is
            real.
 * ``grid``: the paper's speed-comparison design: N(0, I_p), z = alpha * 1_p.
+* ``observations``: the depth of every observation (queries = the sample) on
+           seeded stand-ins with the shapes of the paper's two real data sets
+           (Section 5.1; the data themselves are not available): ``"scores"``,
+           64 rows of four strongly correlated scores that rise from column to
+           column, rounded to 0.01; ``"returns"``, 500 rows of four weakly
+           correlated heavy-tailed (Student-t, 4 degrees of freedom) daily
+           returns of scale 0.015, rounded to 1e-6.  As in the paper, p = 3
+           uses the first three columns and a smaller n the first n rows.
 
 Degenerate families for parity tests (small n, heavy exact degeneracy):
 ``lattice_small``, ``ray_duplicated``, ``rank_deficient``, ``near_degenerate``,
@@ -39,7 +47,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = [
-    "c1", "c2", "c3", "c4", "c5", "grid", "config",
+    "c1", "c2", "c3", "c4", "c5", "grid", "observations", "config",
     "lattice_small", "ray_duplicated", "rank_deficient", "near_degenerate",
     "symmetric", "duplicated", "outside_hull_query", "unimodular",
 ]
@@ -202,6 +210,31 @@ def grid(p: int, n: int, alpha: float, seed: int = 0):
     X = rng.standard_normal((n, p))
     Z = np.full((1, p), float(alpha))
     return _f64(X), _f64(Z)
+
+
+def observations(kind: str, p: int, n: int, seed: int = 6):
+    """Sample whose every observation is a query (Z = X).  ``kind`` is
+    ``"scores"`` (up to 64 rows) or ``"returns"`` (up to 500 rows); p <= 4."""
+    rng = np.random.default_rng(seed)
+    if kind == "scores":
+        rows = 64
+        S = np.full((4, 4), 0.8) + 0.2 * np.eye(4)
+        mu = np.array([0.0, 0.5, 1.0, 1.5])
+        A = mu + 2.0 * rng.standard_normal((rows, 4)) @ np.linalg.cholesky(S).T
+        A = np.round(A, 2)
+    elif kind == "returns":
+        rows = 500
+        rng = np.random.default_rng(seed + 1)
+        S = np.full((4, 4), 0.1) + 0.9 * np.eye(4)
+        G = rng.standard_normal((rows, 4)) @ np.linalg.cholesky(S).T
+        W = rng.chisquare(4.0, size=(rows, 1))
+        A = np.round(0.015 * G / np.sqrt(W / 4.0), 6)
+    else:
+        raise KeyError(kind)
+    if not (1 <= p <= 4 and 1 <= n <= rows):
+        raise ValueError("observations(%r): p <= 4 and n <= %d" % (kind, rows))
+    X = _f64(A[:n, :p])
+    return X, X.copy()
 
 
 def config(name: str):
