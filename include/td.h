@@ -89,7 +89,9 @@ typedef enum {
 typedef struct {
     int32_t precision;         /* td_precision (default TD_PREC_FP32_FILTERED) */
     int32_t autotune;          /* 1: use the tuned launch shape when cached */
-    int32_t chunk;             /* subsets per work item (multiple of 64), 0 = auto */
+    int32_t chunk;             /* subsets per work item (multiple of 64), 0 = auto (256, halved
+                                  down to 64 while there are fewer than four items per
+                                  resident wave) */
     int32_t grid_blocks;       /* persistent blocks, 0 = auto */
     double filter_scale;       /* scales the float32 error radius: 1 normal,
                                   +inf re-checks every float32 decision,

@@ -341,7 +341,31 @@ td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_optio
             qcls.push_back(c);
         }
     }
-    if (chunk == 0) chunk = 256;
+    if (chunk == 0) {
+        // default: 256 ranks per item, halved (down to one batch of 64) while
+        // the class with the most subsets has fewer than four items per
+        // resident wave, so that a call with little work per query (p = 3,
+        // or few queries) still spreads over every compute unit
+        chunk = 256;
+        int big = -1;
+        uint64_t most = 0;
+        std::vector<uint64_t> subs(plan->cls.size(), 0);
+        for (const QueryDesc& d : plan->qd)
+            if (d.cls >= 0) subs[d.cls] += binom_host(d.n, d.p - 2);
+        for (size_t c = 0; c < subs.size(); ++c)
+            if (subs[c] > most) { most = subs[c]; big = (int)c; }
+        if (big >= 0) {
+            const uint64_t want = 4ull * (uint64_t)dc->num_cu *
+                                  (uint64_t)resident_blocks(dc, tier, plan->cls[big].p, plan->cls[big].K);
+            while (chunk > 64) {
+                uint64_t it = 0;
+                for (const QueryDesc& d : plan->qd)
+                    if (d.cls == big) it += (binom_host(d.n, d.p - 2) + chunk - 1) / chunk;
+                if (it >= want) break;
+                chunk /= 2;
+            }
+        }
+    }
     plan->chunk = chunk;
     // group queries by class so that every class owns a contiguous item range
     std::vector<int> order(plan->qd.size());
