@@ -71,8 +71,8 @@ def algorithmic_ops(m: int, p: int) -> float:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -236,8 +236,8 @@ def main():
 
 def bench_c4(a, td, workloads, torch, np, dev):
     """256 datasets of uneven n and p (8 queries each): one td_depth_batched
-    call (one captured graph launch) against one plain float64 td_depth call
-    per query."""
+    call (one captured graph launch; median of 3 timed launches) against one
+    plain float64 td_depth call per query (one pass)."""
     def note(msg):
         print("[c4] %s" % msg, file=sys.stderr, flush=True)
 
@@ -263,11 +263,15 @@ def bench_c4(a, td, workloads, torch, np, dev):
     td.depth_batched(probs)       # captures the graph
     torch.cuda.synchronize()
     note("warm-up launch done")
-    t = time.time()
-    outs = td.depth_batched(probs)
-    torch.cuda.synchronize()
-    tb = time.time() - t
-    note("timed graph launch: %.2f s" % tb)
+    runs = []
+    outs = None
+    for _ in range(3):
+        t = time.time()
+        outs = td.depth_batched(probs)
+        torch.cuda.synchronize()
+        runs.append(time.time() - t)
+        note("timed graph launch: %.2f s" % runs[-1])
+    tb = sorted(runs)[1]   # median of 3
     st = td.get_stats()
     t = time.time()
     plain = []
@@ -284,7 +288,7 @@ def bench_c4(a, td, workloads, torch, np, dev):
     res = {"metric": "c4 batched: sweeps/s of one graph launch (float32-filtered, exact)",
            "value": sweeps / tb, "unit": "sweeps/s", "n_gpus": 1, "data": "synthetic",
            "config": {"workload": "c4: 256 datasets, p in {3,4,5}, n in [50,800], 8 queries each"},
-           "sweeps": sweeps, "batched_s": tb, "plain_launches": len(pl), "plain_s": tp,
+           "sweeps": sweeps, "batched_s": tb, "batched_runs_s": runs, "plain_launches": len(pl), "plain_s": tp,
            "plain_sweeps_per_s": sweeps / tp, "speedup_batched_vs_plain_launches": tp / tb,
            "mismatches_batched_vs_plain": int(np.sum(got != pl)),
            "deferred_subsets": st["deferred_subsets"], "device_status": st["device_status"]}
