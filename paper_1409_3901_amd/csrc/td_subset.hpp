@@ -803,33 +803,37 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     }
     int best = kBig, defer = 0;
     if (lane == 0) {
+        // every entry is read from LDS once, as one 16-byte load: `nx` holds
+        // the entry after the current cluster (zero past the end)
+        const uint4 kNone = make_uint4(0u, 0u, 0u, 0u);
+        uint4 nx = gtot > 0 ? list[0] : kNone;
         int k = 0;
 #pragma unroll 1
         while (k < gtot && !defer) {
-            const uint32_t run = list[k].z >> 11;
-            int s = (int)(list[k].z & 0x7ffu);
+            const uint32_t run = nx.z >> 11;
+            int s = (int)(nx.z & 0x7ffu);
             int a = k;
 #pragma unroll 1
-            while (a < gtot && (list[a].z >> 11) == run && !defer) {
-                // cluster: maximal run of overlapping intervals
-                const uint4 va = list[a];
+            while (a < gtot && (nx.z >> 11) == run && !defer) {
+                // cluster: maximal run of overlapping intervals, with the
+                // count of its positive-fold points
+                const uint4 va = nx;
                 uint32_t mhi = va.x + (va.y & 0x7fffffffu);
-                int hp = (va.y & kAuxNeg) ? 0 : 1, hn = 1 - hp;
+                int npos_c = (va.y & kAuxNeg) ? 0 : 1;
                 int b = a;
-                while (b + 1 < gtot && (list[b + 1].z >> 11) == run &&
-                       list[b + 1].x - (list[b + 1].y & 0x7fffffffu) <= mhi) {
+                nx = (b + 1 < gtot) ? list[b + 1] : kNone;
+#pragma unroll 1
+                while (b + 1 < gtot && (nx.z >> 11) == run && nx.x - (nx.y & 0x7fffffffu) <= mhi) {
                     ++b;
-                    const uint4 vb = list[b];
-                    mhi = max(mhi, vb.x + (vb.y & 0x7fffffffu));
-                    hp |= (vb.y & kAuxNeg) ? 0 : 1;
-                    hn |= (vb.y & kAuxNeg) ? 1 : 0;
+                    mhi = max(mhi, nx.x + (nx.y & 0x7fffffffu));
+                    npos_c += (nx.y & kAuxNeg) ? 0 : 1;
+                    nx = (b + 1 < gtot) ? list[b + 1] : kNone;
                 }
                 const int c = b - a + 1;
+                const int hp = npos_c > 0 ? 1 : 0, hn = npos_c < c ? 1 : 0;
                 // states inside the run lie in [s - (pos in run), s + (neg in
                 // run)]: if min(S, m - S) cannot go below the bound there, the
                 // inner order does not matter
-                int npos_c = 0;
-                for (int u = a; u <= b; ++u) npos_c += (list[u].y & kAuxNeg) ? 0 : 1;
                 const int dip = min(s - npos_c, m - (s + (c - npos_c)));
                 const bool needed = dip < min(min(U, ubound), best);
                 if (hp && hn && !needed) {
