@@ -1,8 +1,9 @@
 // Host side of the C ABI declared in include/td.h.
 //
 // One engine serves td_depth_ex and td_depth_batched.  The queries of a call
-// are grouped by class (p, K): K = sort width / 64, the number of points each
-// lane holds.  Every class gets a contiguous range of work items (a work item
+// are grouped by class (p, Kk): Kk is the number of points each lane of the
+// subset kernel holds, K = sort width / 64 except where the bucketed sweep
+// runs a narrower kernel (kernel_k).  Every class gets a contiguous range of work items (a work item
 // is `chunk` consecutive subset ranks of one query) and its own persistent
 // subset kernel; per-call data (query descriptors, class ranges) lives in
 // device memory, so kernel arguments do not change between calls and the
@@ -250,8 +251,17 @@ td_status check_problem(const Problem& pr) {
 // 3 filtered with the bucketed sweep.  The exact precision runs a filtered
 // kernel with every subset deferred to the exact tier.
 int subset_tier(const td_options& o) {
-    if (o.precision == TD_PREC_FP64_PLAIN) return 0;
-    return o.sweep == TD_SWEEP_BITONIC ? 1 : 3;
+    if (o.precision == TD_PREC_FP64_PLAIN) return td::kPlain;
+    return o.sweep == TD_SWEEP_BITONIC ? td::kFilt : td::kFiltBucket;
+}
+
+// Points per lane of the subset kernel for a sample of n points whose sort
+// width is M = 64 K.  The bucketed sweep needs no power-of-two width, so a
+// sample of 512 < n <= 768 at p <= 6 runs 12 points per lane instead of 16
+// (a quarter of the padding and of the point registers less).
+int kernel_k(int tier, int p, int64_t n, int K) {
+    if (tier == td::kFiltBucket && K == 16 && p <= 6 && n <= 768) return 12;
+    return K;
 }
 
 std::string tune_key(int tier, int p, int K) {
@@ -274,6 +284,7 @@ int resident_blocks(DeviceCtx* dc, int tier, int p, int K) {
 
 struct ClassPlan {
     int p = 0, K = 0, M = 0;
+    int Kk = 0;               // points per lane of the subset kernel
     Shape shape;
     int xblocks = 0;          // exact-tier grid
     uint64_t items = 0;
@@ -301,11 +312,13 @@ td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_optio
         if (pr.m == 0) continue;
         const int M = std::max(64, next_pow2((int)pr.n));
         const int K = M / 64;
+        const int Kk = kernel_k(tier, pr.p, pr.n, K);
         int ib = 0;
         while ((1 << ib) < M) ++ib;
         int c = -1;
         if (pr.p >= 2) {
-            auto key = std::make_pair((int)pr.p, K);
+            // (p, Kk) fixes M as well: Kk differs from K only for M = 1024
+            auto key = std::make_pair((int)pr.p, Kk);
             auto it = slot.find(key);
             if (it == slot.end()) {
                 if ((int)plan->cls.size() == td::kMaxClasses) return TD_ERR_UNSUPPORTED;
@@ -314,8 +327,9 @@ td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_optio
                 ClassPlan cp;
                 cp.p = pr.p;
                 cp.K = K;
+                cp.Kk = Kk;
                 cp.M = M;
-                auto tt = dc->tuned.find(tune_key(tier, pr.p, K));
+                auto tt = dc->tuned.find(tune_key(tier, pr.p, Kk));
                 if (o.autotune && tt != dc->tuned.end()) {
                     cp.shape = tt->second;
                     if (chunk == 0) chunk = tt->second.chunk;
@@ -356,7 +370,7 @@ td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_optio
             if (subs[c] > most) { most = subs[c]; big = (int)c; }
         if (big >= 0) {
             const uint64_t want = 4ull * (uint64_t)dc->num_cu *
-                                  (uint64_t)resident_blocks(dc, tier, plan->cls[big].p, plan->cls[big].K);
+                                  (uint64_t)resident_blocks(dc, tier, plan->cls[big].p, plan->cls[big].Kk);
             while (chunk > 64) {
                 uint64_t it = 0;
                 for (const QueryDesc& d : plan->qd)
@@ -402,7 +416,7 @@ td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_optio
     uint64_t soff = 0;
     for (ClassPlan& cp : plan->cls) {
         // default: every compute unit filled to the kernel's occupancy
-        int blocks = cp.shape.blocks > 0 ? cp.shape.blocks : dc->num_cu * resident_blocks(dc, tier, cp.p, cp.K);
+        int blocks = cp.shape.blocks > 0 ? cp.shape.blocks : dc->num_cu * resident_blocks(dc, tier, cp.p, cp.Kk);
         if ((uint64_t)blocks > cp.items) blocks = (int)std::max<uint64_t>(1, cp.items);
         cp.shape.blocks = blocks;
         cp.xblocks = dc->num_cu * 4;
@@ -435,7 +449,7 @@ td_status enqueue(const Plan& plan, const Pools& base, const td_options& o, hipS
         pl.wscratch_bytes = cp.scratch_per_block;
         hipError_t e = tier == 0   ? td_launch_subset_plain(cp.p, cp.K, cp.shape.blocks, s, &pl)
                        : tier == 1 ? td_launch_subset_filt(cp.p, cp.K, cp.shape.blocks, s, &pl)
-                                   : td_launch_subset_bucket(cp.p, cp.K, cp.shape.blocks, s, &pl);
+                                   : td_launch_subset_bucket(cp.p, cp.Kk, cp.shape.blocks, s, &pl);
         if (e != hipSuccess) return TD_ERR_HIP;
     }
     if (timing) HIPCHK(hipEventRecord(w->ev[2], s));
@@ -462,8 +476,9 @@ std::string graph_signature(const Plan& plan, const Pools& pl, const td_options&
                      std::to_string(pl.chunk) + "|" + std::to_string(pl.defer_cap) + "|" +
                      std::to_string(pl.sweep_mode) + "|" + std::to_string(pl.prune);
     for (const ClassPlan& cp : plan.cls) {
-        k += "|" + std::to_string(cp.p) + "," + std::to_string(cp.K) + "," + std::to_string(cp.shape.blocks) + "," +
-             std::to_string(cp.scratch_per_block) + "," + std::to_string(cp.items > 0);
+        k += "|" + std::to_string(cp.p) + "," + std::to_string(cp.K) + "," + std::to_string(cp.Kk) + "," +
+             std::to_string(cp.shape.blocks) + "," + std::to_string(cp.scratch_per_block) + "," +
+             std::to_string(cp.items > 0);
     }
     return k;
 }
@@ -747,8 +762,8 @@ td_status td_autotune(int32_t p, int64_t n, const td_options* base, void* stream
         DeviceCtx* dctx = nullptr;
         if (ensure_device(dev, &dctx) == TD_OK) num_cu = dctx->num_cu;
     }
-    const int K = std::max(64, next_pow2((int)n)) / 64;
     const int tier = subset_tier(o);
+    const int K = kernel_k(tier, p, n, std::max(64, next_pow2((int)n)) / 64);
     float best = 1e30f;
     Shape bs;
     const int chunks[] = {64, 128, 256, 512};

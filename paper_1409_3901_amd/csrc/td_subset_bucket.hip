@@ -12,6 +12,10 @@ KernelFn pick_k(int K) {
         case 2: return subset_kernel<P, 2, kFiltBucket>;
         case 4: return subset_kernel<P, 4, kFiltBucket>;
         case 8: return subset_kernel<P, 8, kFiltBucket>;
+        case 12:
+            // samples of 512 < n <= 768 (the sweep needs no power-of-two width)
+            if constexpr (P <= 6) return subset_kernel<P, 12, kFiltBucket>;
+            return nullptr;
         case 16: return subset_kernel<P, 16, kFiltBucket>;
     }
     return nullptr;

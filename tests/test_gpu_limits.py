@@ -53,3 +53,44 @@ def test_largest_sample(td, dev, prec, p):
     st = td.get_stats()
     assert st["device_status"] == 0
     assert np.array_equal(got, exp), (got, exp)
+
+
+# Samples of 512 < n <= 768 at p <= 6 run the bucketed kernel with 12 points
+# per lane instead of 16; n = 513 and 768 are its ends, 769 the first sample
+# back on 16.
+@pytest.mark.parametrize("p,n", [(3, 513), (3, 768), (3, 769), (4, 513), (4, 768), (4, 769)])
+def test_twelve_points_per_lane(td, dev, p, n):
+    rng = np.random.default_rng(200 + 7 * p + n)
+    X = rng.standard_normal((n, p))
+    X[-3:] = X[:3]   # duplicated observations (n0 = 2 for the sample queries)
+    Z = np.vstack([rng.standard_normal((2, p)), X[:1], X[n // 2:n // 2 + 1], 3.0 * rng.standard_normal((1, p))])
+    exp = oracle.depth_counts(X, Z)
+    got = run(td, dev, X, Z)
+    assert td.get_stats()["device_status"] == 0
+    assert np.array_equal(got, exp), (got, exp)
+
+
+def test_twelve_points_per_lane_p5(td, dev):
+    """p = 5, n = 600: the bucketed kernel (12 points per lane) against the
+    full bitonic sort and the plain float64 tier (16 points per lane), which
+    order the points independently of it."""
+    rng = np.random.default_rng(601)
+    X = rng.standard_normal((600, 5))
+    Z = np.vstack([0.2 * rng.standard_normal((2, 5)), X[:1], 2.5 * rng.standard_normal((1, 5))])
+    a = run(td, dev, X, Z)
+    assert td.get_stats()["device_status"] == 0
+    b = run(td, dev, X, Z, **PREC_OPTS["bitonic"])
+    c = run(td, dev, X, Z, **PREC_OPTS["plain"])
+    assert np.array_equal(a, b), (a, b)
+    assert np.array_equal(a, c), (a, c)
+
+
+def test_twelve_points_per_lane_p6(td, dev):
+    """p = 6, n = 520, one central query: bucketed against bitonic."""
+    rng = np.random.default_rng(520)
+    X = rng.standard_normal((520, 6))
+    Z = np.zeros((1, 6))
+    a = run(td, dev, X, Z)
+    assert td.get_stats()["device_status"] == 0
+    b = run(td, dev, X, Z, **PREC_OPTS["bitonic"])
+    assert np.array_equal(a, b), (a, b)
