@@ -73,7 +73,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain float64 comparison legs (c3 and --c4)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -277,25 +278,27 @@ def bench_c4(a, td, workloads, torch, np, dev):
         note("timed graph launch: %.2f s" % runs[-1])
     tb = sorted(runs)[1]   # median of 3
     st = td.get_stats()
-    t = time.time()
-    plain = []
-    for i, (Xd, Zd) in enumerate(probs):
-        for q in range(Zd.shape[0]):
-            plain.append(td.depth(Xd, Zd[q:q + 1].contiguous(), precision="plain"))
-        if i % 32 == 31:
-            torch.cuda.synchronize()
-            note("plain launches: %d datasets, %.1f s" % (i + 1, time.time() - t))
-    torch.cuda.synchronize()
-    tp = time.time() - t
-    got = np.concatenate([o.cpu().numpy() for o in outs])
-    pl = np.concatenate([o.cpu().numpy() for o in plain])
     res = {"metric": "c4 batched: sweeps/s of one graph launch (float32-filtered, exact)",
            "value": sweeps / tb, "unit": "sweeps/s", "n_gpus": 1, "data": "synthetic",
            "config": {"workload": "c4: 256 datasets, p in {3,4,5}, n in [50,800], 8 queries each"},
-           "sweeps": sweeps, "batched_s": tb, "batched_runs_s": runs, "plain_launches": len(pl), "plain_s": tp,
-           "plain_sweeps_per_s": sweeps / tp, "speedup_batched_vs_plain_launches": tp / tb,
-           "mismatches_batched_vs_plain": int(np.sum(got != pl)),
+           "sweeps": sweeps, "batched_s": tb, "batched_runs_s": runs,
            "deferred_subsets": st["deferred_subsets"], "device_status": st["device_status"]}
+    if not a.no_plain:
+        t = time.time()
+        plain = []
+        for i, (Xd, Zd) in enumerate(probs):
+            for q in range(Zd.shape[0]):
+                plain.append(td.depth(Xd, Zd[q:q + 1].contiguous(), precision="plain"))
+            if i % 32 == 31:
+                torch.cuda.synchronize()
+                note("plain launches: %d datasets, %.1f s" % (i + 1, time.time() - t))
+        torch.cuda.synchronize()
+        tp = time.time() - t
+        got = np.concatenate([o.cpu().numpy() for o in outs])
+        pl = np.concatenate([o.cpu().numpy() for o in plain])
+        res.update({"plain_launches": len(pl), "plain_s": tp, "plain_sweeps_per_s": sweeps / tp,
+                    "speedup_batched_vs_plain_launches": tp / tb,
+                    "mismatches_batched_vs_plain": int(np.sum(got != pl))})
     print(json.dumps(res), flush=True)
 
 
