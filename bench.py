@@ -253,14 +253,14 @@ def bench_c4(a, td, workloads, torch, np, dev):
             sweeps += math.comb(n - n0, p - 2)
     note("%d sweeps" % sweeps)
     # launch shapes tuned per kernel class, at the class's largest n: points
-    # per lane k = sort width / 64, except that the bucketed sweep runs 12 for
-    # 512 < n <= 768 at p <= 6
+    # per lane k = sort width / 64, except that the bucketed sweep runs 10, 12
+    # or 14 for 512 < n <= 896 at p <= 6
     classes = {}
     for X, Z in data:
         n, p = X.shape
         k = max(64, 1 << (n - 1).bit_length()) // 64
-        if k == 16 and p <= 6 and n <= 768:
-            k = 12
+        if k == 16 and p <= 6 and n <= 896:
+            k = (n + 127) // 128 * 2
         classes[(p, k)] = max(classes.get((p, k), 0), n)
     for (p, k), n in sorted(classes.items()):
         td.autotune(p, n)

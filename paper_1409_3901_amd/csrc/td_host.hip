@@ -257,10 +257,11 @@ int subset_tier(const td_options& o) {
 
 // Points per lane of the subset kernel for a sample of n points whose sort
 // width is M = 64 K.  The bucketed sweep needs no power-of-two width, so a
-// sample of 512 < n <= 768 at p <= 6 runs 12 points per lane instead of 16
-// (a quarter of the padding and of the point registers less).
+// sample of 512 < n <= 896 at p <= 6 runs 10, 12 or 14 points per lane
+// instead of 16 (padded points cost the same work as real ones, and fewer
+// point registers leave fewer spills).
 int kernel_k(int tier, int p, int64_t n, int K) {
-    if (tier == td::kFiltBucket && K == 16 && p <= 6 && n <= 768) return 12;
+    if (tier == td::kFiltBucket && K == 16 && p <= 6 && n <= 896) return (int)((n + 127) / 128) * 2;
     return K;
 }
 

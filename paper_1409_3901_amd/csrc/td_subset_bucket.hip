@@ -12,9 +12,16 @@ KernelFn pick_k(int K) {
         case 2: return subset_kernel<P, 2, kFiltBucket>;
         case 4: return subset_kernel<P, 4, kFiltBucket>;
         case 8: return subset_kernel<P, 8, kFiltBucket>;
+        // samples of 512 < n <= 896 in steps of 128 (the sweep needs no
+        // power-of-two width)
+        case 10:
+            if constexpr (P <= 6) return subset_kernel<P, 10, kFiltBucket>;
+            return nullptr;
         case 12:
-            // samples of 512 < n <= 768 (the sweep needs no power-of-two width)
             if constexpr (P <= 6) return subset_kernel<P, 12, kFiltBucket>;
+            return nullptr;
+        case 14:
+            if constexpr (P <= 6) return subset_kernel<P, 14, kFiltBucket>;
             return nullptr;
         case 16: return subset_kernel<P, 16, kFiltBucket>;
     }

@@ -55,11 +55,12 @@ def test_largest_sample(td, dev, prec, p):
     assert np.array_equal(got, exp), (got, exp)
 
 
-# Samples of 512 < n <= 768 at p <= 6 run the bucketed kernel with 12 points
-# per lane instead of 16; n = 513 and 768 are its ends, 769 the first sample
-# back on 16.
-@pytest.mark.parametrize("p,n", [(3, 513), (3, 768), (3, 769), (4, 513), (4, 768), (4, 769)])
-def test_twelve_points_per_lane(td, dev, p, n):
+# Samples of 512 < n <= 896 at p <= 6 run the bucketed kernel with 10, 12 or
+# 14 points per lane instead of 16 (n up to 640, 768, 896); every end of those
+# ranges, and 897, the first sample back on 16.
+@pytest.mark.parametrize("p,n", [(3, 513), (3, 640), (3, 641), (3, 768), (3, 769), (3, 896), (3, 897),
+                                 (4, 513), (4, 640), (4, 641), (4, 768), (4, 769), (4, 896), (4, 897)])
+def test_narrow_points_per_lane(td, dev, p, n):
     rng = np.random.default_rng(200 + 7 * p + n)
     X = rng.standard_normal((n, p))
     X[-3:] = X[:3]   # duplicated observations (n0 = 2 for the sample queries)
@@ -70,12 +71,13 @@ def test_twelve_points_per_lane(td, dev, p, n):
     assert np.array_equal(got, exp), (got, exp)
 
 
-def test_twelve_points_per_lane_p5(td, dev):
-    """p = 5, n = 600: the bucketed kernel (12 points per lane) against the
+@pytest.mark.parametrize("n", [600, 700, 850])
+def test_narrow_points_per_lane_p5(td, dev, n):
+    """p = 5: the bucketed kernel (10, 12 and 14 points per lane) against the
     full bitonic sort and the plain float64 tier (16 points per lane), which
     order the points independently of it."""
-    rng = np.random.default_rng(601)
-    X = rng.standard_normal((600, 5))
+    rng = np.random.default_rng(n + 1)
+    X = rng.standard_normal((n, 5))
     Z = np.vstack([0.2 * rng.standard_normal((2, 5)), X[:1], 2.5 * rng.standard_normal((1, 5))])
     a = run(td, dev, X, Z)
     assert td.get_stats()["device_status"] == 0
@@ -85,8 +87,9 @@ def test_twelve_points_per_lane_p5(td, dev):
     assert np.array_equal(a, c), (a, c)
 
 
-def test_twelve_points_per_lane_p6(td, dev):
-    """p = 6, n = 520, one central query: bucketed against bitonic."""
+def test_narrow_points_per_lane_p6(td, dev):
+    """p = 6, n = 520 (10 points per lane), one central query: bucketed
+    against bitonic."""
     rng = np.random.default_rng(520)
     X = rng.standard_normal((520, 6))
     Z = np.zeros((1, 6))
