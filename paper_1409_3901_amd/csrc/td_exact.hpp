@@ -29,6 +29,11 @@ struct XS {
 };
 
 constexpr int kExactClusterMax = 64;
+
+// Lower end of a key interval [q - rq, q + rq], clamped at 0.  Keys are sorted
+// by lower end, so that a lower end above every earlier upper end (lower end
+// + 2 rq) is a strict gap of the exact order, whatever the radii.
+__device__ __forceinline__ uint64_t lower_end64(uint64_t q, uint32_t rq) { return q > rq ? q - rq : 0ull; }
 constexpr int kDeltaMax = 16;       // |K_I| handled by the hitting-set search
 constexpr int kCircuitMax = 128;
 
@@ -378,7 +383,7 @@ __global__ __launch_bounds__(64) void exact_kernel(Pools pl) {
             if (key64(y1, y2, eps, pos, t, r) && r * qscale < (double)kWide) {
                 const uint64_t qv = min((uint64_t)(t * qscale), qmax);
                 const uint32_t rq = (uint32_t)(r * qscale) + 3u;
-                key[i] = (qv << 10) | (uint64_t)idx;
+                key[i] = (lower_end64(qv, rq) << 10) | (uint64_t)idx;
                 sside[idx] = rq | (pos ? 0u : 0x80000000u);
                 nplus += pos ? 1 : 0;
             } else {
@@ -413,14 +418,14 @@ __global__ __launch_bounds__(64) void exact_kernel(Pools pl) {
                 while (i < mcert) {
                     const uint64_t k0 = skey[i];
                     const uint32_t sd0 = sside[k0 & 1023u];
-                    int64_t mhi = (int64_t)(k0 >> 10) + (int64_t)(sd0 & 0x7fffffffu);
+                    int64_t mhi = (int64_t)(k0 >> 10) + 2 * (int64_t)(sd0 & 0x7fffffffu);
                     int np = (sd0 >> 31) ? 0 : 1;
                     int j = i;
                     while (j + 1 < mcert) {
                         const uint64_t kk = skey[j + 1];
                         const uint32_t sd = sside[kk & 1023u];
-                        if ((int64_t)(kk >> 10) - (int64_t)(sd & 0x7fffffffu) > mhi) break;
-                        mhi = max(mhi, (int64_t)(kk >> 10) + (int64_t)(sd & 0x7fffffffu));
+                        if ((int64_t)(kk >> 10) > mhi) break;
+                        mhi = max(mhi, (int64_t)(kk >> 10) + 2 * (int64_t)(sd & 0x7fffffffu));
                         np += (sd >> 31) ? 0 : 1;
                         ++j;
                     }
@@ -483,7 +488,7 @@ __global__ __launch_bounds__(64) void exact_kernel(Pools pl) {
                     // the float64 frame cannot place it: refuse rather than guess
                     atomicOr(&s_flag, 1);
                 }
-                key[i] = (qv << 10) | (uint64_t)idx;
+                key[i] = (lower_end64(qv, rq) << 10) | (uint64_t)idx;
                 sside[idx] = rq | (sig > 0 ? 0u : 0x80000000u);
                 nplus += sig > 0 ? 1 : 0;
             }
@@ -516,17 +521,17 @@ __global__ __launch_bounds__(64) void exact_kernel(Pools pl) {
                 const uint64_t k0 = skey[i];
                 const uint32_t sd0 = sside[k0 & 1023u];
                 const int64_t q0 = (int64_t)(k0 >> 10);
-                int64_t mhi = q0 + (int64_t)(sd0 & 0x7fffffffu);
+                int64_t mhi = q0 + 2 * (int64_t)(sd0 & 0x7fffffffu);
                 const int d0 = (sd0 >> 31) ? 1 : -1;
                 bool mixed = false;
                 int j = i;
                 while (j + 1 < m) {
                     const uint64_t kk = skey[j + 1];
                     const uint32_t sd = sside[kk & 1023u];
-                    const int64_t qq = (int64_t)(kk >> 10);
+                    const int64_t qq = (int64_t)(kk >> 10);   // lower end
                     const int64_t rr = (int64_t)(sd & 0x7fffffffu);
-                    if (qq - rr > mhi) break;
-                    mhi = max(mhi, qq + rr);
+                    if (qq > mhi) break;
+                    mhi = max(mhi, qq + 2 * rr);
                     if (((sd >> 31) ? 1 : -1) != d0) mixed = true;
                     ++j;
                 }

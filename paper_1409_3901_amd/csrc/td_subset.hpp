@@ -176,6 +176,20 @@ __device__ __forceinline__ bool key64(double y1, double y2, double eps, bool& po
     return true;
 }
 
+// Lower end of a key interval [q - rq, q + rq] in quanta, clamped at 0 (a
+// lower end taken lower only widens the interval).
+__device__ __forceinline__ uint32_t lower_end(uint32_t q, uint32_t rq) { return q > rq ? q - rq : 0u; }
+
+// Float64 interval [lo, lo + w] holding [t - r, t + r], for the re-ordering of
+// uncertain runs: with r' = r + 8 u64 and t in [0, 2], lo = fl(t - r') errs
+// by at most 2 u64 and stays below t - r; w = 2 r' rounded up to float32, and
+// fl(lo + w) stays above t + r.
+__device__ __forceinline__ void interval64(double t, double r, double& lo, float& w) {
+    const double rr = r + 8.0 * kU64;
+    lo = t - rr;
+    w = (float)(2.0 * rr * 1.0000001) + 1e-30f;
+}
+
 template <int P, int K>
 __device__ int sweep_filt(const float (&xr)[K][P], const SlotFilt<P>& S,
                           const SlotF64<P>& S64, int nnz, const FiltCtx& fc, uint16_t* side, const Staging& sg,
@@ -242,7 +256,10 @@ __device__ int sweep_filt(const float (&xr)[K][P], const SlotFilt<P>& S,
         // idx < M always: the side entry of a point that is not swept is
         // written but never read
         side[idx] = (uint16_t)(rq | (pos ? 0u : kSideNeg));
-        key[i] = (valid && ok) ? ((q << ib) | (uint32_t)idx) : 0xffffffffu;
+        // the sort key is the interval's lower end (clamped at 0, which only
+        // widens the interval), so that a lower end above every earlier upper
+        // end is a strict gap of the exact order
+        key[i] = (valid && ok) ? ((lower_end(q, rq) << ib) | (uint32_t)idx) : 0xffffffffu;
         weak |= (valid && !ok) ? (1u << i) : 0u;
         nplus += (valid && ok && pos) ? 1 : 0;
     }
@@ -264,7 +281,7 @@ __device__ int sweep_filt(const float (&xr)[K][P], const SlotFilt<P>& S,
             if (key64(d1, d2, eps64, pos, t, r) && r * qscale < (double)kRqMax) {
                 const uint32_t q = min((uint32_t)(t * qscale), qmax);
                 const uint32_t rq = (uint32_t)(r * qscale) + 4u;
-                wk[i] = (q << ib) | (uint32_t)idx;
+                wk[i] = (lower_end(q, rq) << ib) | (uint32_t)idx;
                 side[idx] = (uint16_t)(rq | (pos ? 0u : kSideNeg));
                 nplus += pos ? 1 : 0;
             } else {
@@ -280,21 +297,25 @@ __device__ int sweep_filt(const float (&xr)[K][P], const SlotFilt<P>& S,
     wave_sort<K>(key);
     const int m = nnz - KS;
     const int S0 = wave_sum(nplus);
-    // Pass 1: per-lane sum of delta and max of the interval ends.
+    // Pass 1: per-lane sum of delta and max of the interval ends (upper end
+    // = lower end + 2 rq).
     int loc = 0, lmax = -kBig;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const bool real = key[i] != 0xffffffffu;
         const uint32_t sd = side[key[i] & imask];   // in bounds for pads too
         loc += real ? ((sd & kSideNeg) ? 1 : -1) : 0;
-        lmax = real ? max(lmax, (int)(key[i] >> ib) + (int)(sd & 0x7fffu)) : lmax;
+        lmax = real ? max(lmax, (int)(key[i] >> ib) + 2 * (int)(sd & 0x7fffu)) : lmax;
     }
     const int pm0 = wave_excl_max(lmax, -kBig);
     const int s0 = S0 + wave_excl_sum(loc);
-    // Pass 2: cluster starts (interval disjoint from everything before),
-    // states after each element, and runs holding both fold signs.  The state
-    // after element e is legitimate when e ends a cluster, i.e. when the next
-    // element starts one (checked one element late).
+    // Pass 2: cluster starts, states after each element, and runs holding
+    // both fold signs.  The keys are sorted by lower end, so an element whose
+    // lower end exceeds every earlier upper end starts a cluster: every later
+    // interval starts above it too, and the boundary is a strict gap of the
+    // exact order.  The state after element e is legitimate when e ends a
+    // cluster, i.e. when the next element starts one (checked one element
+    // late).
     int pm = pm0, s = s0;
     uint32_t startm = 0, mixm = 0;
     int best = (lane == 0) ? fside(S0, m) : kBig;
@@ -315,8 +336,8 @@ __device__ int sweep_filt(const float (&xr)[K][P], const SlotFilt<P>& S,
         const int rq = (int)(sd & 0x7fffu);
         const int qv = (int)(key[i] >> ib);
         const int dl = real ? ((sd & kSideNeg) ? 1 : -1) : 0;
-        const int lo = real ? qv - rq : kBig;
-        const int hi = real ? qv + rq : -kBig;
+        const int lo = real ? qv : kBig;
+        const int hi = real ? qv + 2 * rq : -kBig;
         const bool st = real && lo > pm;
         pm = max(pm, hi);
         if (st) startm |= 1u << i;
@@ -367,8 +388,9 @@ __device__ int sweep_filt(const float (&xr)[K][P], const SlotFilt<P>& S,
             while (b + 1 < m && !(pflag[b + 1] & 1)) ++b;
             const int c = b - a + 1;
             if (c > kClusterMax) { defer = 1; continue; }
-            // float64 keys of the run, insertion-sorted in place at the run's own
-            // positions of the LDS staging arrays (runs are disjoint)
+            // float64 intervals of the run, insertion-sorted by lower end in
+            // place at the run's own positions of the LDS staging arrays (runs
+            // are disjoint)
             bool ok = true;
             for (int u = 0; u < c; ++u) {
                 const uint32_t kv = pkey[a + u];
@@ -378,15 +400,17 @@ __device__ int sweep_filt(const float (&xr)[K][P], const SlotFilt<P>& S,
                 fp64_point<P>(fc.x64, S64.e1, S64.e2, idx, d1, d2);
                 const double eps64 = S64.beta64 * (double)fc.nrm[idx];
                 if (!key64(d1, d2, eps64, pos, t, r)) { ok = false; break; }
-                const float rf = (float)(r * 1.0000001) + 1e-30f;   // rounded up
+                double lo;
+                float wd;
+                interval64(t, r, lo, wd);
                 int w = u;
-                while (w > 0 && rt[a + w - 1] > t) {
+                while (w > 0 && rt[a + w - 1] > lo) {
                     rt[a + w] = rt[a + w - 1];
                     rr[a + w] = rr[a + w - 1];
                     --w;
                 }
-                rt[a + w] = t;
-                rr[a + w] = pos ? rf : -rf;   // sign carries the fold
+                rt[a + w] = lo;
+                rr[a + w] = pos ? wd : -wd;   // width; the sign carries the fold
             }
             rechecks += (unsigned long long)c;
             if (!ok) { defer = 1; continue; }
@@ -397,7 +421,7 @@ __device__ int sweep_filt(const float (&xr)[K][P], const SlotFilt<P>& S,
             for (int u = 1; u < c; ++u) {
                 const double tu = rt[a + u];
                 const float ru = rr[a + u];
-                if (tu - (double)fabsf(ru) > mhi) {
+                if (tu > mhi) {
                     // certified gap between u-1 and u: a legitimate state
                     if (hasp && hasn) { ok = false; break; }
                     best = min(best, fside(sc, m));
@@ -405,7 +429,7 @@ __device__ int sweep_filt(const float (&xr)[K][P], const SlotFilt<P>& S,
                 }
                 hasp |= ru < 0.0f;
                 hasn |= ru > 0.0f;
-                mhi = fmax(mhi, tu + (double)fabsf(ru));
+                mhi = fmax(mhi, tu + (double)fabsf(ru));   // upper end
                 sc += (ru < 0.0f) ? 1 : -1;
             }
             if (!ok || (hasp && hasn)) defer = 1;
@@ -777,15 +801,17 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
 #pragma unroll
         for (int i = 0; i < K; ++i)
             if ((gm >> i) & 1u) {
-                list[k] = make_uint4(qk[i], aux[i], rinf[i], (uint32_t)(lane * K + i));
+                // lower end of the interval (q >= W > rq for a placed point)
+                list[k] = make_uint4(qk[i] - (aux[i] & 0x7fffffffu), aux[i], rinf[i], (uint32_t)(lane * K + i));
                 ++k;
             }
     }
     __syncthreads();
-    // Order the gathered points by key (runs are separated by strict gaps, so
-    // the key order keeps every run contiguous and in order): every lane
-    // ranks its two entries against the whole list, equal keys by gathering
-    // position, and writes them to their ranks.
+    // Order the gathered points by the lower ends of their intervals (runs are
+    // separated by strict gaps, so this order keeps every run contiguous and
+    // in order; inside a run, a lower end above every earlier upper end is a
+    // strict gap): every lane ranks its two entries against the whole list,
+    // equal keys by gathering position, and writes them to their ranks.
     {
         static_assert(kListMax <= 128, "two list entries per lane");
         const int j0 = lane, j1 = lane + 64;
@@ -821,14 +847,14 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
                 // cluster: maximal run of overlapping intervals, with the
                 // count of its positive-fold points
                 const uint4 va = nx;
-                uint32_t mhi = va.x + (va.y & 0x7fffffffu);
+                uint32_t mhi = va.x + 2u * (va.y & 0x7fffffffu);   // upper end
                 int npos_c = (va.y & kAuxNeg) ? 0 : 1;
                 int b = a;
                 nx = (b + 1 < gtot) ? list[b + 1] : kNone;
 #pragma unroll 1
-                while (b + 1 < gtot && (nx.z >> 11) == run && nx.x - (nx.y & 0x7fffffffu) <= mhi) {
+                while (b + 1 < gtot && (nx.z >> 11) == run && nx.x <= mhi) {
                     ++b;
-                    mhi = max(mhi, nx.x + (nx.y & 0x7fffffffu));
+                    mhi = max(mhi, nx.x + 2u * (nx.y & 0x7fffffffu));
                     npos_c += (nx.y & kAuxNeg) ? 0 : 1;
                     nx = (b + 1 < gtot) ? list[b + 1] : kNone;
                 }
@@ -856,21 +882,25 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
                         fp64_point<P>(fc.x64, S64.e1, S64.e2, idx, d1, d2);
                         const double eps64 = S64.beta64 * (double)fc.nrm[idx];
                         if (!key64(d1, d2, eps64, pos, t, r)) { ok = false; break; }
-                        const float rf = (float)(r * 1.0000001) + 1e-30f;   // rounded up
+                        double lo;
+                        float wd;
+                        interval64(t, r, lo, wd);
                         int v = u;
-                        while (v > 0 && rt[v - 1] > t) {
+                        while (v > 0 && rt[v - 1] > lo) {
                             rt[v] = rt[v - 1];
                             rr[v] = rr[v - 1];
                             --v;
                         }
-                        rt[v] = t;
-                        rr[v] = pos ? rf : -rf;
+                        rt[v] = lo;
+                        rr[v] = pos ? wd : -wd;
                     }
                     rechecks += (unsigned long long)c;
                     if (!ok) { defer = 1; break; }
-                    // float64 sub-runs of overlapping intervals; one that holds
-                    // both signs is settled only if its states could go below
-                    // the bound (then the subset goes to the exact tier)
+                    // float64 sub-runs of overlapping intervals (sorted by lower
+                    // end: a lower end above every earlier upper end is a
+                    // strict gap); one that holds both signs is settled only
+                    // if its states could go below the bound (then the subset
+                    // goes to the exact tier)
                     double thi = rt[0] + (double)fabsf(rr[0]);
                     int s_sub = s, np_sub = 0, nn_sub = 0;
                     if (rr[0] < 0.0f) ++nn_sub; else ++np_sub;
@@ -879,7 +909,7 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
                     for (int u = 1; u < c; ++u) {
                         const double tu = rt[u];
                         const float ru = rr[u];
-                        if (tu - (double)fabsf(ru) > thi) {
+                        if (tu > thi) {
                             if (np_sub && nn_sub &&
                                 min(s_sub - np_sub, m - (s_sub + nn_sub)) < min(min(U, ubound), best)) {
                                 ok = false;

@@ -113,6 +113,29 @@ def test_forced_fallback(td, dev, mode, sweep):
         assert np.array_equal(got, exp), (p, got, exp)
 
 
+@pytest.mark.parametrize("scale", [16.0, 512.0, 8192.0])
+@pytest.mark.parametrize("sweep", ["auto", "bitonic"])
+def test_widened_float32_radii(td, dev, scale, sweep):
+    """float32 key intervals widened by `scale` next to float64 re-checks of
+    the points that then fail the float32 check: clusters of intervals whose
+    widths differ by orders of magnitude, the case in which the grouping
+    must order intervals by their lower ends.  Counts must not change."""
+    rng = np.random.default_rng(int(scale) + 5)
+    cases = [workloads.c1()]
+    for p, n in [(3, 60), (4, 45), (5, 25)]:
+        X = rng.standard_normal((n, p))
+        cases.append((X, np.vstack([0.3 * rng.standard_normal((2, p)), X[:1]])))
+    for p in (3, 4, 5):
+        cases.append(workloads.near_degenerate(rng, p, 12))
+        cases.append(workloads.lattice_small(rng, p, 11, R=2))
+    bad = []
+    for t, (X, Z) in enumerate(cases):
+        got, exp = _check(td, dev, X, Z, sweep=sweep, filter_scale=scale)
+        if not np.array_equal(got, exp):
+            bad.append((t, X.shape, got.tolist(), exp.tolist()))
+    assert not bad, bad
+
+
 def test_rank_too_low_is_flagged(td, dev):
     """Centred data spanning at most p-3 dimensions is outside what the GPU
     path handles: the query reports -1 and a status bit, never a wrong count."""
