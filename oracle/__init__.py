@@ -9,6 +9,7 @@ its Python binding) never imports, loads or calls anything here.
 * ``depth_range``  -- the same loop restricted to a range of subset ranks (a
   bounded sample, used to time the oracle).
 * ``depth_vertex`` -- the critical-direction route in C++ (tiny inputs).
+* ``enumerate_subsets`` -- the subset ranks as the depth loop visits them.
 * ``brute``        -- independent pure-Python exact arbiters.
 """
 from __future__ import annotations
@@ -60,6 +61,9 @@ def _load():
     lib.oracle_depth_vertex.restype = ctypes.c_int
     lib.oracle_binom.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.oracle_binom.restype = ctypes.c_uint64
+    lib.oracle_enumerate.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64,
+                                     ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]
+    lib.oracle_enumerate.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -120,3 +124,18 @@ def depth_vertex(X, z) -> int:
 
 def binom(n: int, k: int) -> int:
     return int(_load().oracle_binom(n, k))
+
+
+def enumerate_subsets(n: int, k: int, r0: int = 0, r1: int | None = None, chunk: int = 256) -> np.ndarray:
+    """The k-subsets of lexicographic rank [r0, r1) as the depth loop visits
+    them (rows of k indices, rank order)."""
+    lib = _load()
+    total = binom(n, k)
+    r1 = total if r1 is None else min(int(r1), total)
+    cnt = max(0, r1 - int(r0))
+    out = np.zeros((cnt, max(k, 1)), dtype=np.int32)
+    got = lib.oracle_enumerate(int(n), int(k), int(r0), int(r1), int(chunk),
+                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if got != cnt:
+        raise ValueError("oracle_enumerate returned %d, expected %d" % (got, cnt))
+    return out[:, :k]

@@ -631,6 +631,66 @@ void unrank_lex(uint64_t r, int n, int k, std::vector<int>& c) {
     }
 }
 
+// Visits the subsets of lexicographic rank [r0, r1) in rank order, in
+// chunks of `chunk` consecutive ranks: each chunk starts from an unranked
+// subset and steps with next_comb (the loop of Algorithm 1, Step 1, over
+// the index set of (p-2)-subsets, split for the threads).  fn(chunk, rank,
+// subset) is called once per rank; the chunks run in parallel.
+template <typename Fn>
+void visit_range(uint64_t r0, uint64_t r1, int n, int k, uint64_t chunk, Fn&& fn) {
+    if (r1 <= r0) return;
+    const int64_t nchunks = (int64_t)((r1 - r0 + chunk - 1) / chunk);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t ch = 0; ch < nchunks; ++ch) {
+        uint64_t a = r0 + (uint64_t)ch * chunk, b = std::min(r1, a + chunk);
+        std::vector<int> I;
+        unrank_lex(a, n, k, I);
+        for (uint64_t r = a; r < b; ++r) {
+            fn(ch, r, I);
+            if (r + 1 < b) next_comb(I, n);
+        }
+    }
+}
+
+// Minimum of the valid subsets' terms over the ranks [r0, r1) (INT_MAX if
+// none is valid), and the number of subsets visited.
+int thread_slot() {
+#ifdef _OPENMP
+    return omp_get_thread_num();
+#else
+    return 0;
+#endif
+}
+
+int thread_slots() {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+int min_over_range(const Ctx& C, uint64_t r0, uint64_t r1, uint64_t* visited) {
+    const int n = C.P->n, k = C.P->p - 2;
+    // per-thread minimum and count, combined after the loop
+    std::vector<int> best((size_t)thread_slots(), std::numeric_limits<int>::max());
+    std::vector<uint64_t> cnt((size_t)thread_slots(), 0);
+    visit_range(r0, r1, n, k, 256, [&](int64_t, uint64_t, const std::vector<int>& I) {
+        const int t = subset_term(C, I);
+        const size_t w = (size_t)thread_slot();
+        if (t >= 0 && t < best[w]) best[w] = t;
+        ++cnt[w];
+    });
+    int b = std::numeric_limits<int>::max();
+    uint64_t v = 0;
+    for (size_t w = 0; w < best.size(); ++w) {
+        b = std::min(b, best[w]);
+        v += cnt[w];
+    }
+    if (visited) *visited = v;
+    return b;
+}
+
 struct Prepared {
     int n0 = 0;
     int kind = 0;   // 0: use subsets, 1: closed form value in `value`
@@ -698,28 +758,16 @@ int oracle_depth(const double* X, int64_t n, int32_t p, const double* Z, int64_t
         const int k = R.P.p - 2;
         const uint64_t total = binom(R.P.n, k);
         Ctx C{&R.P, xo};
-        int best = std::numeric_limits<int>::max();
-        const uint64_t chunk = 256;
-        const int64_t nchunks = (int64_t)((total + chunk - 1) / chunk);
-#pragma omp parallel for schedule(dynamic, 1) reduction(min : best)
-        for (int64_t ch = 0; ch < nchunks; ++ch) {
-            uint64_t r0 = (uint64_t)ch * chunk, r1 = std::min(total, r0 + chunk);
-            std::vector<int> I;
-            unrank_lex(r0, R.P.n, k, I);
-            for (uint64_t r = r0; r < r1; ++r) {
-                int t = subset_term(C, I);
-                if (t >= 0 && t < best) best = t;
-                if (r + 1 < r1) next_comb(I, R.P.n);
-            }
-        }
+        const int best = min_over_range(C, 0, total, nullptr);
         out[q] = R.n0 + best;   // at least one valid subset exists after the span map
     }
     return 0;
 }
 
 // Minimum of delta_I + b_I over the subsets of lexicographic rank [r0, r1)
-// for one query (a bounded sample of the full loop), plus n0.  Only defined
-// when the centred points span R^p.  *swept receives the number of subsets.
+// for one query (a bounded sample of the full loop), plus n0 (-1 if no
+// subset in the range is valid).  Only defined when the centred points span
+// R^p.  *swept receives the number of subsets visited (counted).
 int oracle_depth_range(const double* X, int64_t n, int32_t p, const double* z, uint64_t r0,
                        uint64_t r1, int64_t* out_min, uint64_t* swept, int32_t threads,
                        int32_t flags) {
@@ -735,22 +783,8 @@ int oracle_depth_range(const double* X, int64_t n, int32_t p, const double* z, u
     r1 = std::min(r1, total);
     if (r0 > r1) r0 = r1;
     Ctx C{&R.P, xo};
-    int best = std::numeric_limits<int>::max();
-    const uint64_t chunk = 256;
-    const int64_t nchunks = (int64_t)((r1 - r0 + chunk - 1) / chunk);
-#pragma omp parallel for schedule(dynamic, 1) reduction(min : best)
-    for (int64_t ch = 0; ch < nchunks; ++ch) {
-        uint64_t a = r0 + (uint64_t)ch * chunk, b = std::min(r1, a + chunk);
-        std::vector<int> I;
-        unrank_lex(a, R.P.n, k, I);
-        for (uint64_t r = a; r < b; ++r) {
-            int t = subset_term(C, I);
-            if (t >= 0 && t < best) best = t;
-            if (r + 1 < b) next_comb(I, R.P.n);
-        }
-    }
+    const int best = min_over_range(C, r0, r1, swept);
     *out_min = (best == std::numeric_limits<int>::max()) ? -1 : (int64_t)(R.n0 + best);
-    *swept = r1 - r0;
     return 0;
 }
 
@@ -780,5 +814,20 @@ int oracle_depth_vertex(const double* X, int64_t n, int32_t p, const double* z, 
 }
 
 uint64_t oracle_binom(int32_t n, int32_t k) { return binom(n, k); }
+
+// The k-subsets of {0..n-1} of lexicographic rank [r0, r1), written in rank
+// order to out (k ints each), visited as the depth loop visits them: chunks
+// of `chunk` ranks, each unranked at its start and stepped with next_comb.
+// Returns the number of subsets written.
+int64_t oracle_enumerate(int32_t n, int32_t k, uint64_t r0, uint64_t r1, uint64_t chunk,
+                         int32_t* out) {
+    if (n < 0 || k < 0 || k > n || !out || chunk == 0) return -1;
+    r1 = std::min(r1, binom(n, k));
+    if (r0 > r1) r0 = r1;
+    visit_range(r0, r1, n, k, chunk, [&](int64_t, uint64_t r, const std::vector<int>& I) {
+        for (int i = 0; i < k; ++i) out[(r - r0) * (uint64_t)k + (uint64_t)i] = I[(size_t)i];
+    });
+    return (int64_t)(r1 - r0);
+}
 
 }  // extern "C"

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include "td_common.hpp"
+#include "td_rank.hpp"
 
 namespace td {
 
@@ -247,31 +248,7 @@ __device__ __forceinline__ void wave_sort(T (&v)[K]) {
     sort_phases<K, 2>(v, lane_id());
 }
 
-// --------------------------------------------------------- binomial / rank
-__device__ __forceinline__ uint64_t binom_lookup(const uint64_t* tab, int n, int k) {
-    if (k < 0 || n < k) return 0;
-    return tab[n * kBinomK + k];
-}
-
-// Colexicographic unranking of k-subsets: rank = sum_i C(c_i, i+1) with
-// c_0 < c_1 < ... < c_{k-1}.  The map does not depend on the ground-set size,
-// so ranks below C(n', k) give subsets of {0..n'-1}.
-template <int KS>
-__device__ __forceinline__ void unrank_colex(const uint64_t* tab, uint64_t r, int nmax, int (&c)[KS > 0 ? KS : 1]) {
-    int hi = nmax;  // exclusive upper bound for the current element
-#pragma unroll
-    for (int i = KS; i >= 1; --i) {
-        // largest x in [i-1, hi-1] with C(x, i) <= r
-        int lo = i - 1, h = hi - 1;
-        while (lo < h) {
-            int mid = (lo + h + 1) >> 1;
-            if (binom_lookup(tab, mid, i) <= r) lo = mid; else h = mid - 1;
-        }
-        c[i - 1] = lo;
-        r -= binom_lookup(tab, lo, i);
-        hi = lo;
-    }
-}
+// Binomial table and colex unranking: td_rank.hpp.
 
 // -------------------------------------------- minors of the p x (p-2) block
 // Combination tables (rows of a p-row matrix) for the Laplace recursion that

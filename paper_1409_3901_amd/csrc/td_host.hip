@@ -20,6 +20,7 @@
 
 #include "../../include/td.h"
 #include "td_common.hpp"
+#include "td_rank.hpp"
 
 extern "C" hipError_t td_launch_init(const td::Pools* pl, hipStream_t s);
 extern "C" hipError_t td_launch_prep(const td::Pools* pl, int blocks, hipStream_t s);
@@ -50,13 +51,7 @@ using td::QueryState;
 
 constexpr int64_t kDefaultDeferCap = 1 << 25;
 
-uint64_t binom_host(int64_t n, int k) {
-    if (k < 0 || n < k) return 0;
-    unsigned __int128 r = 1;
-    for (int i = 1; i <= k; ++i) r = r * (unsigned __int128)(n - k + i) / (unsigned __int128)i;
-    if (r > (unsigned __int128)UINT64_MAX) return UINT64_MAX;
-    return (uint64_t)r;
-}
+using td::binom_host;
 
 int next_pow2(int v) {
     int m = 1;
@@ -134,8 +129,7 @@ td_status ensure_device(int dev, DeviceCtx** out) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) c->num_cu = prop.multiProcessorCount;
     std::vector<uint64_t> tab((size_t)td::kBinomN * td::kBinomK);
-    for (int n = 0; n < td::kBinomN; ++n)
-        for (int k = 0; k < td::kBinomK; ++k) tab[(size_t)n * td::kBinomK + k] = binom_host(n, k);
+    td::fill_binom_table(tab.data());
     if (hipMalloc(&c->binom, tab.size() * sizeof(uint64_t)) != hipSuccess) { delete c; return TD_ERR_OUT_OF_MEMORY; }
     if (hipMemcpy(c->binom, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess) {
         hipFree(c->binom);

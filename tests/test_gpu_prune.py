@@ -112,3 +112,24 @@ def test_batched_pruned_equals_unpruned(td, dev):
     for x, y in zip(a, b):
         assert np.array_equal(x, y), (x, y)
         assert x[-1] == 0
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2", "c3"])
+@pytest.mark.parametrize("prec", ["filtered", "bitonic", "plain"])
+def test_every_subset_accounted_unpruned(td, dev, cfg, prec):
+    """With pruning off, the subset kernels visit every (p-2)-subset of every
+    query once: swept + deferred + invalid = sum over queries of C(n', p-2),
+    n' the observations different from the query (equality, the index set
+    of Section 2)."""
+    from conftest import PREC_OPTS
+    X, Z = workloads.config(cfg)
+    n, p = X.shape
+    total = 0
+    for q in range(Z.shape[0]):
+        n0 = int(np.sum(np.all(X == Z[q], axis=1)))
+        total += workloads_subsets(n - n0, p)
+    _, st = run(td, dev, X, Z, prune=False, **PREC_OPTS[prec])
+    assert st["pruned_subsets"] == 0
+    assert st["device_status"] == 0
+    got = st["subsets_swept"] + st["deferred_subsets"] + st["invalid_subsets"]
+    assert got == total, (got, total, st)
