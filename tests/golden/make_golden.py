@@ -7,6 +7,14 @@ are skipped.
 
     python tests/golden/make_golden.py [c1 c2 c3 c5 c4] [--threads T]
     python tests/golden/make_golden.py c5 --queries 15,14,13 --part b
+    python tests/golden/make_golden.py c4wide wide
+
+c4wide stores, in ``c4.wide.json``, queries of the batched workload's p = 5
+datasets with n > 512 (the kernels holding 10, 12 or 14 points per lane),
+two per kernel class, from the two smallest datasets of each class; they lie
+above the subsample budget.  ``wide`` stores ``wide.json``: the samples of
+``workloads.WIDE_CASES`` at the ends of those classes, keyed
+``"<case>:<query>"`` (query 0 first for every case, then query 1).
 
 c5 is computed on its pre-map integer lattice: the mapped data is its exact
 integer affine image, and the depth does not change under such a map.
@@ -36,6 +44,9 @@ import workloads  # noqa: E402
 
 SEEDS = {"c1": 0, "c2": 2, "c3": 3, "c4": 4, "c5": 5}
 C4_BUDGET = 3.0e8
+# (dataset, query) of c4 at p = 5 above the budget: n = 517, 518 (10 points
+# per lane), 642, 644 (12), 770, 773 (14).
+C4_WIDE = [(159, 0), (224, 1), (137, 0), (218, 1), (3, 0), (221, 1)]
 
 
 def c4_subsample():
@@ -64,7 +75,47 @@ def _save(path, obj):
     os.replace(tmp, path)
 
 
+def run_c4wide(threads: int):
+    path = os.path.join(HERE, "c4.wide.json")
+    obj = _load(path) or {"config": "c4", "seed": SEEDS["c4"], "source": "oracle/td_oracle.cpp",
+                          "subsample_rule": "p = 5, n > 512: two queries per kernel class",
+                          "counts": {}}
+    data = workloads.c4()
+    for d, q in C4_WIDE:
+        key = "%d:%d" % (d, q)
+        if key in obj["counts"]:
+            continue
+        X, Z = data[d]
+        t = time.time()
+        v = int(oracle.depth_counts(X, Z[q:q + 1], threads=threads)[0])
+        obj["counts"][key] = v
+        _save(path, obj)
+        print("c4wide %s (n=%d) -> %d (%.1fs)" % (key, X.shape[0], v, time.time() - t), flush=True)
+
+
+def run_wide(threads: int):
+    path = os.path.join(HERE, "wide.json")
+    obj = _load(path) or {"config": "wide", "source": "oracle/td_oracle.cpp",
+                          "cases": {k: list(v) for k, v in workloads.WIDE_CASES.items()},
+                          "counts": {}}
+    for q in (0, 1):
+        for name in workloads.WIDE_CASES:
+            key = "%s:%d" % (name, q)
+            if key in obj["counts"]:
+                continue
+            X, Z = workloads.wide(name)
+            t = time.time()
+            v = int(oracle.depth_counts(X, Z[q:q + 1], threads=threads)[0])
+            obj["counts"][key] = v
+            _save(path, obj)
+            print("wide %s -> %d (%.1fs)" % (key, v, time.time() - t), flush=True)
+
+
 def run(cfg: str, threads: int, queries=None, part=None):
+    if cfg == "c4wide":
+        return run_c4wide(threads)
+    if cfg == "wide":
+        return run_wide(threads)
     path = os.path.join(HERE, cfg + (".%s" % part if part else "") + ".json")
     obj = _load(path)
     if cfg == "c4":

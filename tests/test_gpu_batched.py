@@ -90,14 +90,25 @@ def test_autotune_then_depth(td, dev):
     assert np.array_equal(got.cpu().numpy(), oracle.depth_counts(X, Z))
 
 
+def c4_golden():
+    """Stored oracle counts of the batched workload, merged over the files
+    c4.json (the budget subsample) and c4.<part>.json (e.g. the p = 5
+    datasets with n > 512 in c4.wide.json)."""
+    g = {}
+    for name in sorted(os.listdir(GOLD)):
+        if name == "c4.json" or (name.startswith("c4.") and name.endswith(".json")):
+            with open(os.path.join(GOLD, name)) as f:
+                g.update(json.load(f)["counts"])
+    return g
+
+
 def test_c4_subsample_golden(td, dev):
     """All 256 datasets of the batched workload in one graph launch; the
-    queries the oracle could afford (stored subsample) must match, the rest
-    must satisfy d <= n0 + floor(n'/2) and d >= 0."""
-    path = os.path.join(GOLD, "c4.json")
-    if not os.path.exists(path):
-        pytest.skip("c4 golden file not generated yet")
-    g = json.load(open(path))["counts"]
+    queries the oracle could afford (stored subsample, plus two queries per
+    wide p = 5 kernel class) must match, the rest must satisfy
+    d <= n0 + floor(n'/2) and d >= 0."""
+    g = c4_golden()
+    assert g, "c4 golden files missing"
     data = workloads.c4()
     dprobs = [(to_dev(X, dev), to_dev(Z, dev)) for X, Z in data]
     outs = [o.cpu().numpy() for o in td.depth_batched(dprobs)]

@@ -3,6 +3,9 @@ dimensions (p = 7, 8, where a subset has 5 or 6 members and the sort classes
 run at one or two waves per SIMD) and the largest sample (n = 1024, the full
 sort width, where p = 2 puts 1024 points in one sweep, more than the bucket
 words count, so every sweep goes to the exact tier)."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -11,6 +14,7 @@ import workloads
 from conftest import PREC_OPTS, to_dev
 
 pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 PRECS = ["filtered", "bitonic", "plain"]
 
@@ -67,6 +71,27 @@ def test_narrow_points_per_lane(td, dev, p, n):
     Z = np.vstack([rng.standard_normal((2, p)), X[:1], X[n // 2:n // 2 + 1], 3.0 * rng.standard_normal((1, p))])
     exp = oracle.depth_counts(X, Z)
     got = run(td, dev, X, Z)
+    assert td.get_stats()["device_status"] == 0
+    assert np.array_equal(got, exp), (got, exp)
+
+
+def _wide_golden():
+    with open(os.path.join(GOLD, "wide.json")) as f:
+        return json.load(f)["counts"]
+
+
+@pytest.mark.parametrize("name", sorted(workloads.WIDE_CASES))
+@pytest.mark.parametrize("prec", ["filtered", "bitonic"])
+def test_wide_classes_vs_stored_oracle(td, dev, name, prec):
+    """Samples at the ends of the kernel classes (p = 5: n = 640, the last
+    sample on 10 points per lane, and n = 768, the last on 12; p = 6: n = 270,
+    8 points per lane) against stored oracle counts, both filtered sweeps."""
+    g = _wide_golden()
+    X, Z = workloads.wide(name)
+    qs = [q for q in range(Z.shape[0]) if "%s:%d" % (name, q) in g]
+    assert qs, "no stored count for %s" % name
+    exp = np.array([g["%s:%d" % (name, q)] for q in qs])
+    got = run(td, dev, X, Z[qs], **PREC_OPTS[prec])
     assert td.get_stats()["device_status"] == 0
     assert np.array_equal(got, exp), (got, exp)
 

@@ -49,7 +49,8 @@ import numpy as np
 __all__ = [
     "c1", "c2", "c3", "c4", "c5", "grid", "observations", "config",
     "lattice_small", "ray_duplicated", "rank_deficient", "near_degenerate",
-    "symmetric", "duplicated", "outside_hull_query", "unimodular",
+    "symmetric", "duplicated", "outside_hull_query", "unimodular", "wide",
+    "WIDE_CASES",
 ]
 
 
@@ -235,6 +236,26 @@ def observations(kind: str, p: int, n: int, seed: int = 6):
         raise ValueError("observations(%r): p <= 4 and n <= %d" % (kind, rows))
     X = _f64(A[:n, :p])
     return X, X.copy()
+
+
+# Samples sized at the ends of the kernel classes that hold 10, 12 or 14
+# points per lane (p = 5, 512 < n <= 896) and of the 8-points-per-lane class
+# at p = 6 (260 < n <= 516): name -> (p, n, seed).
+WIDE_CASES = {
+    "p5n640": (5, 640, 640),
+    "p5n768": (5, 768, 768),
+    "p6n270": (6, 270, 270),
+}
+
+
+def wide(name: str):
+    """N(0, I_p) sample of one of ``WIDE_CASES`` with two queries: a deep
+    point 0.3 * N(0, I_p) and a sample point (n0 = 1)."""
+    p, n, seed = WIDE_CASES[name]
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, p))
+    Z = np.vstack([0.3 * rng.standard_normal((1, p)), X[n // 3:n // 3 + 1]])
+    return _f64(X), _f64(Z)
 
 
 def config(name: str):
