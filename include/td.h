@@ -127,6 +127,9 @@ typedef struct {
                                     exact order (TD_SWEEP_AUTO) */
     uint64_t pruned_subsets;     /* subsets skipped because the query's
                                     minimum had already reached 0 (prune) */
+    uint64_t exact_subsets;      /* deferred subsets the exact tier took up:
+                                    each deferred subset once, so this equals
+                                    min(deferred_subsets, deferred_capacity) */
 } td_stats;
 
 /* One independent depth problem of a batch (pointers as for td_depth). */
@@ -142,19 +145,36 @@ typedef struct {
 /* Fills *out with the defaults. */
 td_status td_default_options(td_options* out);
 
-/* Depth counts of the m queries Z w.r.t. X with the default options. */
+/* Depth counts of the m queries Z w.r.t. X with the default options.
+ * counts[q] = n * D_n(Z_q), the sample halfspace depth of Section 1,
+ * equation (1), computed by Algorithm 1 (loop over the (p-2)-subsets, each
+ * step the bivariate sort and sweep of Algorithm 2; Proposition 1 with
+ * r = p-2, equation (8)); the integer count of Algorithm 1, Step 2.
+ * X: n x p, Z: m x p, row-major float64, counts: m int32, all device memory
+ * owned by the caller.  p = 1 uses the closed form of Section 3; p = 2 runs
+ * Algorithm 2 once on the centred points.  Errors: TD_ERR_INVALID_ARG for a
+ * null pointer, p outside [1, TD_MAX_P], n outside [1, TD_MAX_N] or m < 0
+ * (synchronous, counts untouched); per-query failures as counts[q] = -1 with
+ * a TD_DEV_* bit. */
 td_status td_depth(const double* X, int64_t n, int32_t p, const double* Z, int64_t m,
                    int32_t* counts, void* stream);
 
-/* As td_depth with explicit options (NULL = defaults). */
+/* As td_depth with explicit options (NULL = defaults): the arithmetic tier
+ * (Algorithm 2 in float32 with certified error bounds, plain float64, or
+ * exact), the order of the sweep, the bound of Algorithm 3, Step 2(a), and
+ * the launch shape.  An invalid option returns TD_ERR_INVALID_ARG. */
 td_status td_depth_ex(const double* X, int64_t n, int32_t p, const double* Z, int64_t m,
                       int32_t* counts, const td_options* opt, void* stream);
 
-/* Many independent problems of uneven n and p in one captured HIP graph
- * launch: one preparation kernel, one persistent subset kernel pulling
- * (query, subset-range) work items from a device counter, the exact tier and
- * the finalisation.  `probs` is a HOST array read during the call; the
- * pointers inside follow the td_depth conventions. */
+/* Many independent problems of uneven n and p (each as td_depth: Section 1,
+ * equation (1), by Algorithm 1 with Algorithm 2) in one captured HIP graph
+ * launch: one preparation kernel, one persistent subset kernel per (p,
+ * points-per-lane) class pulling (query, subset-range) work items from a
+ * device counter, the exact tier and the finalisation.  `probs` is a HOST
+ * array of `num` problems read during the call; the pointers inside follow
+ * the td_depth conventions.  TD_ERR_INVALID_ARG for num < 0, a null array or
+ * an invalid problem; TD_ERR_UNSUPPORTED for more than 2^30 queries or a
+ * query with more than 2^32 work items. */
 td_status td_depth_batched(const td_problem* probs, int32_t num, const td_options* opt,
                            void* stream);
 

@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(HERE, "_lib", "libtd.so")
 
 TD_OK = 0
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported request", 3: "out of device memory",
-          4: "HIP runtime error", 5: "some queries failed (see device_status)", 6: "no HIP device"}
+          4: "HIP runtime error", 5: "some queries failed (see device_status)", 6: "no HIP device",
+          7: "call too large for the static workspace"}
 PRECISION = {"plain": 0, "fp64": 0, "filtered": 1, "fp32": 1, "exact": 2}
 SWEEP = {"auto": 0, "bucket": 0, "bitonic": 1}
 DEV_BITS = {1: "nonfinite", 2: "no_valid_subset", 4: "defer_overflow", 8: "exact_range",
@@ -61,6 +62,7 @@ class Stats(ctypes.Structure):
         ("total_ms", ctypes.c_float),
         ("walked_sweeps", ctypes.c_uint64),
         ("pruned_subsets", ctypes.c_uint64),
+        ("exact_subsets", ctypes.c_uint64),
     ]
 
 

@@ -54,7 +54,13 @@ struct Deferred {
     uint64_t rank;
 };
 
-constexpr int kMaxClasses = 40;   // (p, K) classes of one call
+// (p, K) classes of one call: p = 2..kMaxP with K = 1, 2, 4, 8, 16 points per
+// lane, plus the bucketed sweep's 10, 12 and 14 points per lane at p <= 6.
+constexpr int kNumPow2K = 5;
+constexpr int kNarrowMaxP = 6;
+constexpr int kNumNarrowK = 3;
+constexpr int kMaxClasses = (kMaxP - 1) * kNumPow2K + (kNarrowMaxP - 1) * kNumNarrowK;
+static_assert(kMaxClasses == 50, "class count");
 
 // Device counters accumulated per call (cleared by the init kernel).
 struct Counters {
@@ -67,6 +73,7 @@ struct Counters {
     unsigned long long walked;        // bucketed sweeps that needed the exact walk
     unsigned long long pruned;        // subsets of work items skipped once the
                                       // query's minimum had reached 0
+    unsigned long long exact_done;    // deferred subsets the exact tier processed
     unsigned long long defer_next;    // deferred-queue write position
     unsigned long long prep_next;     // query counter of the preparation kernel
     unsigned long long work_next[kMaxClasses];   // work-item counter per class
@@ -80,6 +87,8 @@ struct CallParams {
     uint64_t cls_begin[kMaxClasses];  // global work items [begin, end) per class
     uint64_t cls_end[kMaxClasses];
     uint64_t cls_scratch[kMaxClasses];// byte offset of the class's block scratch
+    uint32_t cls_chunk[kMaxClasses];  // subsets per work item of the class
+                                      // (multiple of 64)
 };
 
 // Pools of per-query arrays (offsets QueryDesc::v_off in values for the AoS
@@ -98,7 +107,6 @@ struct Pools {
     Deferred* deferred;
     Counters* ctr;
     uint64_t defer_cap;
-    int32_t chunk;      // subsets per work item (multiple of 64)
     float filter_scale;
     int32_t force_exact;
     int32_t cls;        // class slot of this launch (subset and exact kernels)

@@ -291,11 +291,12 @@ __global__ __launch_bounds__(64) void exact_kernel(Pools pl) {
     const int lane = lane_id();
     ExactScratch<P>* X = reinterpret_cast<ExactScratch<P>*>(pl.wscratch + pl.cp->cls_scratch[pl.cls] +
                                                             (uint64_t)blockIdx.x * pl.wscratch_bytes);
-    unsigned long long swept = 0, preds = 0, degen = 0, ninvalid = 0;
+    unsigned long long taken = 0, preds = 0, degen = 0, ninvalid = 0;
     const unsigned long long nd = pl.ctr->defer_next;
     const unsigned long long total = nd < pl.defer_cap ? nd : pl.defer_cap;
     // Static striding over the deferred list: every class launch scans the
-    // whole list and takes the entries of its own class.
+    // whole list and takes the entries of its own class (the class index:
+    // classes of one sort width M differ in points per lane).
     unsigned long long it = blockIdx.x;
     constexpr double qscale = 4503599627370496.0;     // 2^52: t' in [0,2] -> 53 bits
     constexpr uint64_t qmax = (1ull << 54) - 2ull;
@@ -305,7 +306,8 @@ __global__ __launch_bounds__(64) void exact_kernel(Pools pl) {
         const int q = uni((int)dfr.query);
         const QueryDesc d = pl.qd[q];
         const QueryState st = pl.qs[q];
-        if (d.p != P || d.M != M) continue;   // belongs to another class
+        if (d.cls != pl.cls) continue;   // belongs to another class
+        ++taken;
         const int nnz = uni(st.nnz);
         const double* x64 = pl.x64 + d.v_off;
         const float* nrm = pl.nrm + d.n_off;
@@ -438,10 +440,7 @@ __global__ __launch_bounds__(64) void exact_kernel(Pools pl) {
             }
             lb = __builtin_amdgcn_readfirstlane(lb);
             __syncthreads();
-            if (lb >= qbest) {
-                ++swept;
-                continue;
-            }
+            if (lb >= qbest) continue;
         }
         if (lane == 0) { s_nextra = 0; s_flag = 0; }
         if (__any(weak != 0)) {
@@ -598,10 +597,10 @@ __global__ __launch_bounds__(64) void exact_kernel(Pools pl) {
             if (status) atomicOr(&pl.qs[q].status, status);
             else atomicMin(&pl.qs[q].min_term, term);
         }
-        ++swept;
         __syncthreads();
     }
     if (lane == 0) {
+        if (taken) atomicAdd(&pl.ctr->exact_done, taken);
         if (preds) atomicAdd(&pl.ctr->exact_preds, preds);
         if (degen) atomicAdd(&pl.ctr->degenerate, degen);
         if (ninvalid) atomicAdd(&pl.ctr->invalid, ninvalid);

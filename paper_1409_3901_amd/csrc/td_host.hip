@@ -113,7 +113,10 @@ struct DeviceCtx {
 };
 
 struct LastCall {
-    Workspace* ws = nullptr;
+    Workspace* ws = nullptr;        // null after an allocation-free call
+    int device = -1;
+    const Counters* ctr = nullptr;  // device counters and query states of the call
+    const QueryState* qs = nullptr;
     int nq = 0;
     int timing = 0;   // 1: per stage, 2: whole call only
 };
@@ -280,6 +283,7 @@ int resident_blocks(DeviceCtx* dc, int tier, int p, int K) {
 struct ClassPlan {
     int p = 0, K = 0, M = 0;
     int Kk = 0;               // points per lane of the subset kernel
+    int chunk = 0;            // subsets per work item
     Shape shape;
     int xblocks = 0;          // exact-tier grid
     uint64_t items = 0;
@@ -291,17 +295,19 @@ struct Plan {
     std::vector<QueryDesc> qd;
     std::vector<ClassPlan> cls;
     size_t values = 0, points = 0, scratch = 0;
-    int chunk = 256;
     int prep_blocks = 1, fin_blocks = 1;
 };
+
+// The class set fits CallParams: (p, Kk) with p = 2..TD_MAX_P and Kk one of
+// kernel_k's values (1, 2, 4, 8, 16, and 10, 12, 14 at p <= 6).
+static_assert(td::kMaxClasses >= (TD_MAX_P - 1) * 5 + 5 * 3, "every (p, Kk) class of one call");
 
 td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_options& o, Plan* plan) {
     const int tier = subset_tier(o);
     std::map<std::pair<int, int>, int> slot;
     std::vector<int> qcls;
-    // one chunk for the whole call: the explicit option, else the tuned
-    // chunk of the first class, else 256
-    int chunk = o.chunk;
+    // chunk per class: the explicit option, else the class's tuned chunk,
+    // else the default below
     for (int i = 0; i < num; ++i) {
         const Problem& pr = probs[i];
         if (pr.m == 0) continue;
@@ -324,10 +330,11 @@ td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_optio
                 cp.K = K;
                 cp.Kk = Kk;
                 cp.M = M;
+                cp.chunk = o.chunk;
                 auto tt = dc->tuned.find(tune_key(tier, pr.p, Kk));
                 if (o.autotune && tt != dc->tuned.end()) {
                     cp.shape = tt->second;
-                    if (chunk == 0) chunk = tt->second.chunk;
+                    if (cp.chunk == 0) cp.chunk = tt->second.chunk;
                 }
                 if (o.grid_blocks > 0) cp.shape.blocks = o.grid_blocks;
                 plan->cls.push_back(cp);
@@ -350,32 +357,23 @@ td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_optio
             qcls.push_back(c);
         }
     }
-    if (chunk == 0) {
+    for (size_t c = 0; c < plan->cls.size(); ++c) {
+        ClassPlan& cp = plan->cls[c];
+        if (cp.chunk != 0) continue;
         // default: 256 ranks per item, halved (down to one batch of 64) while
-        // the class with the most subsets has fewer than four items per
-        // resident wave, so that a call with little work per query (p = 3,
-        // or few queries) still spreads over every compute unit
-        chunk = 256;
-        int big = -1;
-        uint64_t most = 0;
-        std::vector<uint64_t> subs(plan->cls.size(), 0);
-        for (const QueryDesc& d : plan->qd)
-            if (d.cls >= 0) subs[d.cls] += binom_host(d.n, d.p - 2);
-        for (size_t c = 0; c < subs.size(); ++c)
-            if (subs[c] > most) { most = subs[c]; big = (int)c; }
-        if (big >= 0) {
-            const uint64_t want = 4ull * (uint64_t)dc->num_cu *
-                                  (uint64_t)resident_blocks(dc, tier, plan->cls[big].p, plan->cls[big].Kk);
-            while (chunk > 64) {
-                uint64_t it = 0;
-                for (const QueryDesc& d : plan->qd)
-                    if (d.cls == big) it += (binom_host(d.n, d.p - 2) + chunk - 1) / chunk;
-                if (it >= want) break;
-                chunk /= 2;
-            }
+        // the class has fewer than four items per resident wave, so that a
+        // class with little work per query (p = 3, or few queries) still
+        // spreads over every compute unit
+        cp.chunk = 256;
+        const uint64_t want = 4ull * (uint64_t)dc->num_cu * (uint64_t)resident_blocks(dc, tier, cp.p, cp.Kk);
+        while (cp.chunk > 64) {
+            uint64_t it = 0;
+            for (const QueryDesc& d : plan->qd)
+                if (d.cls == (int)c) it += (binom_host(d.n, d.p - 2) + cp.chunk - 1) / cp.chunk;
+            if (it >= want) break;
+            cp.chunk /= 2;
         }
     }
-    plan->chunk = chunk;
     // group queries by class so that every class owns a contiguous item range
     std::vector<int> order(plan->qd.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
@@ -399,6 +397,7 @@ td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_optio
         d.items = 0;
         if (d.cls >= 0) {
             const uint64_t nsub = binom_host(d.n, d.p - 2);
+            const uint64_t chunk = (uint64_t)plan->cls[d.cls].chunk;
             const uint64_t it = (nsub + chunk - 1) / chunk;
             if (it > 0xffffffffull) return TD_ERR_UNSUPPORTED;
             d.items = (uint32_t)it;
@@ -468,7 +467,7 @@ std::string graph_signature(const Plan& plan, const Pools& pl, const td_options&
     std::string k = std::to_string(subset_tier(o)) + "|" + std::to_string(w->generation) + "|" +
                      std::to_string(plan.prep_blocks) + "|" + std::to_string(plan.fin_blocks) + "|" +
                      std::to_string(pl.force_exact) + "|" + std::to_string(pl.filter_scale) + "|" +
-                     std::to_string(pl.chunk) + "|" + std::to_string(pl.defer_cap) + "|" +
+                     std::to_string(pl.defer_cap) + "|" +
                      std::to_string(pl.sweep_mode) + "|" + std::to_string(pl.prune);
     for (const ClassPlan& cp : plan.cls) {
         k += "|" + std::to_string(cp.p) + "," + std::to_string(cp.K) + "," + std::to_string(cp.Kk) + "," +
@@ -539,6 +538,7 @@ td_status run(const Problem* probs, int num, const td_options& o, hipStream_t st
         acc += plan.cls[c].items;
         cph->cls_end[c] = acc;
         cph->cls_scratch[c] = plan.cls[c].scratch_off;
+        cph->cls_chunk[c] = (uint32_t)plan.cls[c].chunk;
     }
     std::memcpy(w->staging + sizeof(CallParams), plan.qd.data(), (size_t)nq * sizeof(QueryDesc));
     HIPCHK(hipMemcpyAsync(w->cp, cph, sizeof(CallParams), hipMemcpyHostToDevice, stream));
@@ -560,7 +560,6 @@ td_status run(const Problem* probs, int num, const td_options& o, hipStream_t st
     pl.deferred = w->deferred;
     pl.ctr = w->ctr;
     pl.defer_cap = (uint64_t)dcap;
-    pl.chunk = plan.chunk;
     pl.filter_scale = std::isinf(o.filter_scale) ? 3.0e38f : (float)o.filter_scale;
     pl.force_exact = (o.force_exact || o.precision == TD_PREC_EXACT) ? 1 : 0;
     pl.sweep_mode = o.sweep;
@@ -568,6 +567,9 @@ td_status run(const Problem* probs, int num, const td_options& o, hipStream_t st
     pl.wscratch = w->wscratch;
 
     g_last.ws = w;
+    g_last.device = w->device;
+    g_last.ctr = w->ctr;
+    g_last.qs = w->qs;
     g_last.nq = nq;
     if (!use_graph) {
         g_last.timing = o.timing ? 1 : 0;
@@ -682,11 +684,11 @@ td_status td_get_stats(td_stats* out) {
     std::lock_guard<std::mutex> lk(g_mu);
     std::memset(out, 0, sizeof(*out));
     Workspace* w = g_last.ws;
-    if (!w) return TD_OK;
-    HIPCHK(hipSetDevice(w->device));
+    if (!g_last.ctr) return TD_OK;
+    HIPCHK(hipSetDevice(g_last.device));
     HIPCHK(hipDeviceSynchronize());
     Counters c;
-    HIPCHK(hipMemcpy(&c, w->ctr, sizeof(c), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&c, g_last.ctr, sizeof(c), hipMemcpyDeviceToHost));
     out->subsets_swept = c.swept;
     out->fp64_rechecks = c.fp64_rechecks;
     out->deferred_subsets = c.deferred;
@@ -695,13 +697,14 @@ td_status td_get_stats(td_stats* out) {
     out->invalid_subsets = c.invalid;
     out->walked_sweeps = c.walked;
     out->pruned_subsets = c.pruned;
+    out->exact_subsets = c.exact_done;
     std::vector<QueryState> qs(g_last.nq);
-    if (g_last.nq > 0) HIPCHK(hipMemcpy(qs.data(), w->qs, qs.size() * sizeof(QueryState), hipMemcpyDeviceToHost));
+    if (g_last.nq > 0) HIPCHK(hipMemcpy(qs.data(), g_last.qs, qs.size() * sizeof(QueryState), hipMemcpyDeviceToHost));
     int dst = 0;
     for (auto& s : qs) dst |= (s.status & 0xff);
     out->device_status = dst;
     float a = 0;
-    if (g_last.timing == 1) {
+    if (g_last.timing == 1 && w) {
         hipEventElapsedTime(&a, w->ev[0], w->ev[1]);
         out->prep_ms = a;
         hipEventElapsedTime(&a, w->ev[1], w->ev[2]);
@@ -711,7 +714,7 @@ td_status td_get_stats(td_stats* out) {
         hipEventElapsedTime(&a, w->ev[3], w->ev[4]);
         out->finalize_ms = a;
     }
-    if (g_last.timing) {
+    if (g_last.timing && w) {
         hipEventElapsedTime(&a, w->ev[0], w->ev[4]);
         out->total_ms = a;
     }

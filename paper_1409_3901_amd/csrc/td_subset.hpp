@@ -1,8 +1,8 @@
 // The subset kernel: Algorithm 1's loop over (p-2)-subsets with Algorithm 2
 // (projection, angular sort, circular sweep) as the per-subset step.
 //
-// Layout: one wave64 per workgroup.  A work item is a range of `chunk`
-// consecutive colex ranks of one query; waves pull items from a device
+// Layout: one wave64 per workgroup.  A work item is a range of `chunk` (per
+// class) consecutive colex ranks of one query; waves pull items from a device
 // counter until none is left (persistent grid).  The points of the current
 // query stay in registers: lane L holds points L*K .. L*K+K-1 (blocked), so
 // the sort starts with element e = point e.  Bases are built 64 at a time,
@@ -1016,6 +1016,7 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
     fc.fscale = pl.filter_scale;
     const uint64_t cbeg = pl.cp->cls_begin[pl.cls];
     const uint64_t cend = pl.cp->cls_end[pl.cls];
+    const uint32_t chunk = pl.cp->cls_chunk[pl.cls];
     const int nq = pl.cp->num_queries;
     while (true) {
         unsigned long long item = 0;
@@ -1028,8 +1029,8 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
         if (st.status & kStNonfinite) continue;
         const int nnz = uni(st.nnz);
         const uint64_t nsub = uni64(binom_lookup(pl.binom, nnz, KS));
-        const uint64_t r0 = uni64((item - d.item_begin) * (uint64_t)pl.chunk);
-        const uint64_t r1 = uni64(min(r0 + (uint64_t)pl.chunk, nsub));
+        const uint64_t r0 = uni64((item - d.item_begin) * (uint64_t)chunk);
+        const uint64_t r1 = uni64(min(r0 + (uint64_t)chunk, nsub));
         if (r0 >= r1) continue;
         const double* x64 = pl.x64 + d.v_off;
         fc.x64 = x64;

@@ -31,13 +31,22 @@ def test_exports_every_declared_symbol(lib):
         assert hasattr(lib, name), name
 
 
-def test_struct_layouts_match_header():
-    """The binding's ctypes structures have the sizes of the C structures."""
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's ctypes structures have the size and field offsets of the
+    C structures (tests/abi_layout.c compiled against include/td.h)."""
+    import subprocess
     import paper_1409_3901_amd as td
-    # sizeof(td_options), sizeof(td_problem), sizeof(td_stats) on x86-64
-    assert ctypes.sizeof(td.Options) == 48
-    assert ctypes.sizeof(td.Problem) == 48
-    assert ctypes.sizeof(td.Stats) == 88
+    exe = str(tmp_path / "abi_layout")
+    subprocess.check_call(["gcc", "-std=c99", "-O0", os.path.join(ROOT, "tests", "abi_layout.c"), "-o", exe])
+    out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    c = dict(line.split() for line in out if line.strip())
+    for cname, py in (("td_options", td.Options), ("td_stats", td.Stats), ("td_problem", td.Problem)):
+        assert int(c[cname]) == ctypes.sizeof(py), cname
+        names = [f for f, _ in py._fields_]
+        cfields = [k.split(".", 1)[1] for k in c if k.startswith(cname + ".")]
+        assert cfields == names, (cname, cfields, names)
+        for f in names:
+            assert int(c["%s.%s" % (cname, f)]) == getattr(py, f).offset, (cname, f)
 
 
 def test_status_strings_and_version(lib):

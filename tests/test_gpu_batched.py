@@ -119,3 +119,65 @@ def test_c4_subsample_golden(td, dev):
         for q in range(Z.shape[0]):
             n0 = int(np.sum(np.all(X == Z[q], axis=1)))
             assert 0 <= o[q] <= n0 + (X.shape[0] - n0) // 2
+
+
+def _class_n(K):
+    """Smallest sample size whose sort width is 64 K (K a power of two) or,
+    for 10, 12, 14 points per lane, the first size of that range."""
+    return {1: 30, 2: 65, 4: 129, 8: 257, 16: 897, 10: 513, 12: 641, 14: 769}[K]
+
+
+def test_batched_more_than_forty_classes(td, dev):
+    """One call whose problems fall into 47 (p, points-per-lane) classes:
+    p = 2..6 with 1, 2, 4, 8, 16 points per lane and 10, 12, 14 (bucketed
+    sweep), p = 7 up to 8 and p = 8 up to 4.  Every problem has a query
+    outside the hull (depth 0, which the pruning settles quickly) and the
+    small ones a deep query checked against the oracle."""
+    rng = np.random.default_rng(47)
+    probs, deep = [], []
+    classes = [(p, K) for p in range(2, 7) for K in (1, 2, 4, 8, 16, 10, 12, 14)]
+    classes += [(7, K) for K in (1, 2, 4, 8)] + [(8, K) for K in (1, 2, 4)]
+    assert len(classes) == 47
+    for p, K in classes:
+        n = max(_class_n(K), p + 2)
+        X = rng.standard_normal((n, p))
+        Z = workloads.outside_hull_query(X, rng)
+        cheap = K <= 2 and p <= 6 or K == 1
+        if cheap:
+            Z = np.vstack([Z, 0.2 * rng.standard_normal((1, p))])
+        probs.append((X, Z))
+        deep.append(cheap)
+    outs = td.depth_batched([(to_dev(X, dev), to_dev(Z, dev)) for X, Z in probs])
+    st = td.get_stats()
+    assert st["device_status"] == 0, st
+    for (X, Z), o, c in zip(probs, outs, deep):
+        o = o.cpu().numpy()
+        assert o[0] == 0, (X.shape, o)
+        if c:
+            assert o[1] == oracle.depth_counts(X, Z[1:2])[0], (X.shape, o)
+
+
+def test_batched_exact_tier_takes_each_deferred_subset_once(td, dev):
+    """Four p = 5 problems whose kernels hold 10, 12, 14 and 16 points per
+    lane share the sort width 1024.  A point duplicated along its ray from
+    the query sends the subsets holding it to the exact tier; each deferred
+    subset must be taken up by exactly one exact-tier launch, and the counts
+    must equal the single calls'."""
+    rng = np.random.default_rng(48)
+    probs = []
+    for n in (600, 700, 850, 1000):
+        X = rng.standard_normal((n, 5))
+        z = 0.2 * rng.standard_normal(5)
+        X[1] = z + 2.0 * (X[0] - z)
+        probs.append((X, np.vstack([z, 0.3 * rng.standard_normal((1, 5))])))
+    dprobs = [(to_dev(X, dev), to_dev(Z, dev)) for X, Z in probs]
+    outs = td.depth_batched(dprobs, prune=False)
+    st = td.get_stats()
+    assert st["device_status"] == 0, st
+    assert st["deferred_subsets"] > 0
+    assert st["exact_subsets"] == st["deferred_subsets"], st
+    for (Xd, Zd), o in zip(dprobs, outs):
+        single = td.depth(Xd, Zd, prune=False)
+        s1 = td.get_stats()
+        assert s1["exact_subsets"] == s1["deferred_subsets"]
+        assert np.array_equal(o.cpu().numpy(), single.cpu().numpy())
