@@ -56,7 +56,9 @@ typedef enum {
     TD_ERR_OUT_OF_MEMORY = 3, /* workspace allocation failed */
     TD_ERR_HIP = 4,           /* a HIP runtime call failed */
     TD_ERR_DEVICE_STATUS = 5, /* td_get_stats: the last call flagged queries */
-    TD_ERR_NO_DEVICE = 6      /* no HIP device is visible */
+    TD_ERR_NO_DEVICE = 6,     /* no HIP device is visible */
+    TD_ERR_TOO_LARGE = 7      /* td_depth_noalloc: the call needs more than its
+                                 static workspace holds */
 } td_status;
 
 /* Per-query failure bits of td_stats.device_status (OR over the queries). */
@@ -177,6 +179,25 @@ td_status td_depth_ex(const double* X, int64_t n, int32_t p, const double* Z, in
  * query with more than 2^32 work items. */
 td_status td_depth_batched(const td_problem* probs, int32_t num, const td_options* opt,
                            void* stream);
+
+/* As td_depth_ex, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * calls no hipMalloc, hipFree or other allocating routine.  Its workspace is
+ * a static device array of 128 MiB (TD_NOALLOC_BYTES) that every device the
+ * library runs on holds until the process ends; all calls on one device
+ * share it, so calls that overlap on one device (different streams, host
+ * threads) race, while calls ordered on one stream are safe.  The grid is
+ * shrunk to fit the array; a call that does not fit even so (roughly
+ * m * M * p * 36 bytes of per-query arrays, M the sort width >= n, plus the
+ * deferred list and per-block scratch) returns TD_ERR_TOO_LARGE.  At most
+ * 2^18 subsets per call go to the exact tier (deferred_capacity is capped
+ * there); beyond that the query reports TD_DEV_DEFER_OVERFLOW.  The tuned
+ * launch shapes of td_autotune and the timing option are not used; counters
+ * are available from td_get_stats.  Arguments and errors otherwise as
+ * td_depth_ex. */
+#define TD_NOALLOC_BYTES (128ull << 20)
+td_status td_depth_noalloc(const double* X, int64_t n, int32_t p, const double* Z, int64_t m,
+                           int32_t* counts, const td_options* opt, void* stream);
 
 /* Counters and timings of the last call; synchronises the device. */
 td_status td_get_stats(td_stats* out);

@@ -78,8 +78,8 @@ class Problem(ctypes.Structure):
 
 
 # exported symbols of include/td.h
-SYMBOLS = ["td_default_options", "td_depth", "td_depth_ex", "td_depth_batched", "td_get_stats",
-           "td_autotune", "td_status_string", "td_release", "td_version"]
+SYMBOLS = ["td_default_options", "td_depth", "td_depth_ex", "td_depth_batched", "td_depth_noalloc",
+           "td_get_stats", "td_autotune", "td_status_string", "td_release", "td_version"]
 
 _lib = None
 
@@ -107,6 +107,9 @@ def load():
     lib.td_depth_ex.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_int64, vp,
                                 ctypes.POINTER(Options), vp]
     lib.td_depth_ex.restype = ctypes.c_int
+    lib.td_depth_noalloc.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_int64, vp,
+                                     ctypes.POINTER(Options), vp]
+    lib.td_depth_noalloc.restype = ctypes.c_int
     lib.td_depth_batched.argtypes = [ctypes.POINTER(Problem), ctypes.c_int32, ctypes.POINTER(Options), vp]
     lib.td_depth_batched.restype = ctypes.c_int
     lib.td_get_stats.argtypes = [ctypes.POINTER(Stats)]
@@ -177,6 +180,25 @@ def depth(X, Z, stream=None, out=None, **opts):
                          ctypes.c_void_p(out.data_ptr()), ctypes.byref(o), _stream_ptr(stream))
     if rc != TD_OK:
         raise TDError(rc, "td_depth_ex")
+    return out
+
+
+def depth_noalloc(X, Z, out, stream=None, **opts):
+    """As ``depth`` through td_depth_noalloc: the library allocates nothing
+    (its workspace is a static device array); ``out`` (int32, length m, on
+    the device) must be given."""
+    lib = load()
+    _check_tensor(X, "X")
+    _check_tensor(Z, "Z")
+    n, p = X.shape
+    m, pz = Z.shape
+    if pz != p:
+        raise ValueError("X and Z have different dimensions")
+    o = options(**opts)
+    rc = lib.td_depth_noalloc(ctypes.c_void_p(X.data_ptr()), n, p, ctypes.c_void_p(Z.data_ptr()), m,
+                              ctypes.c_void_p(out.data_ptr()), ctypes.byref(o), _stream_ptr(stream))
+    if rc != TD_OK:
+        raise TDError(rc, "td_depth_noalloc")
     return out
 
 

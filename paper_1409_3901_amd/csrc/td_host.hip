@@ -34,6 +34,15 @@ extern "C" int td_resident_blocks_bucket(int P, int K);
 extern "C" hipError_t td_launch_exact(int P, int K, int blocks, hipStream_t s, const td::Pools* pl, int all_items);
 extern "C" uint64_t td_exact_scratch_bytes(int P);
 
+// Workspace of the allocation-free entry point td_depth_noalloc: counters,
+// call parameters, the binomial table, the per-query arrays, the deferred
+// list and the per-block scratch of one call, carved from this array.  Every
+// device the library runs on holds it until the process ends.  In host code
+// `scratch` names a host-side stand-in: the device address comes from
+// hipGetSymbolAddress (per device, at the first call on that device).
+constexpr uint64_t kNoAllocBytes = 128ull << 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
 namespace {
 
 using td::CallParams;
@@ -612,6 +621,202 @@ td_status run(const Problem* probs, int num, const td_options& o, hipStream_t st
     return TD_OK;
 }
 
+// ------------------------------------------------ allocation-free call
+constexpr int kNoAllocMaxDevices = 64;
+constexpr uint64_t kNoAllocDeferCap = 1ull << 18;   // deferred subsets per call
+
+struct NoAllocDev {
+    uint8_t* base = nullptr;    // device address of `scratch` on this device
+    DeviceCtx* ctx = nullptr;   // launch-shape bookkeeping (host only; no binom)
+};
+NoAllocDev g_noalloc[kNoAllocMaxDevices];
+
+// Byte offsets of one call's arrays inside `scratch` (256-byte aligned).
+struct NoAllocLayout {
+    uint64_t ctr, cp, binom, qd, qs, x64, x64lo, x32, xi, nrm, deferred, ws, end;
+};
+
+uint64_t up256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
+
+NoAllocLayout noalloc_layout(uint64_t m, uint64_t M, uint64_t p, uint64_t ws_bytes) {
+    NoAllocLayout L;
+    uint64_t o = 0;
+    L.ctr = o;      o = up256(o + sizeof(Counters));
+    L.cp = o;       o = up256(o + sizeof(CallParams));
+    L.binom = o;    o = up256(o + (uint64_t)td::kBinomN * td::kBinomK * sizeof(uint64_t));
+    L.qd = o;       o = up256(o + m * sizeof(QueryDesc));
+    L.qs = o;       o = up256(o + m * sizeof(QueryState));
+    const uint64_t vals = m * M * p, pts = m * M;
+    L.x64 = o;      o = up256(o + vals * sizeof(double));
+    L.x64lo = o;    o = up256(o + vals * sizeof(double));
+    L.x32 = o;      o = up256(o + vals * sizeof(float));
+    L.xi = o;       o = up256(o + vals * 2 * sizeof(uint64_t));
+    L.nrm = o;      o = up256(o + pts * sizeof(float));
+    L.deferred = o; o = up256(o + kNoAllocDeferCap * sizeof(Deferred));
+    L.ws = o;       o = up256(o + ws_bytes);
+    L.end = o;
+    return L;
+}
+
+// Per-call descriptors written on the device (no host staging): the class
+// ranges of CallParams and one QueryDesc per query of the single problem.
+struct NoAllocArgs {
+    CallParams* cp;
+    QueryDesc* qd;
+    const double* X;
+    const double* Z;
+    int32_t* counts;
+    int32_t n, p, m, M, idx_bits, cls;
+    uint32_t items_per_query, chunk;
+    uint64_t scratch_off;   // class scratch offset (bytes, from pl.wscratch)
+};
+
+__global__ void noalloc_setup_kernel(NoAllocArgs a) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        CallParams c;
+        memset(&c, 0, sizeof(c));
+        c.num_queries = a.m;
+        c.num_classes = a.cls >= 0 ? 1 : 0;
+        c.cls_begin[0] = 0;
+        c.cls_end[0] = a.cls >= 0 ? (uint64_t)a.items_per_query * (uint64_t)a.m : 0;
+        c.cls_scratch[0] = a.scratch_off;
+        c.cls_chunk[0] = a.chunk;
+        *a.cp = c;
+    }
+    for (int q = t; q < a.m; q += gridDim.x * blockDim.x) {
+        QueryDesc d;
+        memset(&d, 0, sizeof(d));
+        d.X = a.X;
+        d.z = a.Z + (size_t)q * a.p;
+        d.count = a.counts + q;
+        d.n = a.n;
+        d.p = a.p;
+        d.M = a.M;
+        d.idx_bits = a.idx_bits;
+        d.v_off = (uint64_t)q * (uint64_t)a.M * (uint64_t)a.p;
+        d.n_off = (uint64_t)q * (uint64_t)a.M;
+        d.items = a.cls >= 0 ? a.items_per_query : 0;
+        d.item_begin = (uint64_t)q * (uint64_t)d.items;
+        d.cls = a.cls;
+        a.qd[q] = d;
+    }
+}
+
+// First call on a device: the device address of `scratch` (with that device
+// current) and the binomial table copied into it once.
+td_status noalloc_device(int dev, NoAllocDev** out) {
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return TD_ERR_UNSUPPORTED;
+    NoAllocDev& d = g_noalloc[dev];
+    if (!d.base) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return TD_ERR_HIP;
+        static uint64_t tab[(size_t)td::kBinomN * td::kBinomK];
+        td::fill_binom_table(tab);
+        const NoAllocLayout L = noalloc_layout(0, 0, 0, 0);
+        if (hipMemcpy((uint8_t*)ptr + L.binom, tab, sizeof(tab), hipMemcpyHostToDevice) != hipSuccess)
+            return TD_ERR_HIP;
+        if (!d.ctx) {
+            d.ctx = new DeviceCtx();
+            hipDeviceProp_t prop;
+            if (hipGetDeviceProperties(&prop, dev) == hipSuccess) d.ctx->num_cu = prop.multiProcessorCount;
+        }
+        d.base = (uint8_t*)ptr;
+    }
+    *out = &d;
+    return TD_OK;
+}
+
+td_status run_noalloc(const Problem& pr, const td_options& o, hipStream_t stream) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return TD_ERR_NO_DEVICE;
+    NoAllocDev* nd = nullptr;
+    td_status st = noalloc_device(dev, &nd);
+    if (st != TD_OK) return st;
+    DeviceCtx* dc = nd->ctx;
+    // the plan of the single problem (one class; none at p = 1); the tuned
+    // shapes of the allocating path are not consulted
+    td_options po = o;
+    po.autotune = 0;
+    Plan plan;
+    st = make_plan(dc, &pr, 1, po, &plan);
+    if (st != TD_OK) return st;
+    const uint64_t m = (uint64_t)pr.m;
+    const uint64_t M = (uint64_t)std::max(64, next_pow2((int)pr.n));
+    int blocks = 0, xblocks = 0;
+    uint64_t per = 256;
+    if (!plan.cls.empty()) {
+        ClassPlan& cp = plan.cls[0];
+        per = cp.scratch_per_block;
+        blocks = cp.items > 0 ? cp.shape.blocks : 0;
+        xblocks = std::min(cp.xblocks, dc->num_cu);
+    }
+    // shrink the grids to what `scratch` holds after the fixed arrays
+    const NoAllocLayout L0 = noalloc_layout(m, M, (uint64_t)pr.p, 0);
+    if (L0.end > kNoAllocBytes) return TD_ERR_TOO_LARGE;
+    const uint64_t fit = (kNoAllocBytes - L0.end) / per;
+    if (!plan.cls.empty() && plan.cls[0].items > 0) {
+        if (fit < 1) return TD_ERR_TOO_LARGE;
+        blocks = (int)std::min<uint64_t>((uint64_t)blocks, fit);
+        xblocks = (int)std::min<uint64_t>((uint64_t)std::max(xblocks, 1), fit);
+        plan.cls[0].shape.blocks = blocks;
+        plan.cls[0].xblocks = xblocks;
+        plan.cls[0].scratch_off = 0;
+    }
+    const uint64_t ws_bytes = per * (uint64_t)std::max(blocks, xblocks);
+    const NoAllocLayout L = noalloc_layout(m, M, (uint64_t)pr.p, ws_bytes);
+    if (L.end > kNoAllocBytes) return TD_ERR_TOO_LARGE;
+
+    uint8_t* b = nd->base;
+    Pools pl;
+    std::memset(&pl, 0, sizeof(pl));
+    pl.x64 = reinterpret_cast<double*>(b + L.x64);
+    pl.x64lo = reinterpret_cast<double*>(b + L.x64lo);
+    pl.x32 = reinterpret_cast<float*>(b + L.x32);
+    pl.nrm = reinterpret_cast<float*>(b + L.nrm);
+    pl.xi = reinterpret_cast<uint64_t*>(b + L.xi);
+    pl.binom = reinterpret_cast<const uint64_t*>(b + L.binom);
+    pl.qs = reinterpret_cast<QueryState*>(b + L.qs);
+    pl.qd = reinterpret_cast<const QueryDesc*>(b + L.qd);
+    pl.cp = reinterpret_cast<const CallParams*>(b + L.cp);
+    pl.deferred = reinterpret_cast<Deferred*>(b + L.deferred);
+    pl.ctr = reinterpret_cast<Counters*>(b + L.ctr);
+    pl.defer_cap = std::min<uint64_t>(kNoAllocDeferCap, o.deferred_capacity > 0 ? (uint64_t)o.deferred_capacity
+                                                                                : kNoAllocDeferCap);
+    pl.filter_scale = std::isinf(o.filter_scale) ? 3.0e38f : (float)o.filter_scale;
+    pl.force_exact = (o.force_exact || o.precision == TD_PREC_EXACT) ? 1 : 0;
+    pl.sweep_mode = o.sweep;
+    pl.prune = (o.prune && subset_tier(o) != 0) ? 1 : 0;
+    pl.wscratch = b + L.ws;
+
+    NoAllocArgs a;
+    a.cp = reinterpret_cast<CallParams*>(b + L.cp);
+    a.qd = reinterpret_cast<QueryDesc*>(b + L.qd);
+    a.X = pr.X;
+    a.Z = pr.Z;
+    a.counts = pr.counts;
+    a.n = (int32_t)pr.n;
+    a.p = pr.p;
+    a.m = (int32_t)pr.m;
+    a.M = (int32_t)M;
+    a.idx_bits = plan.qd[0].idx_bits;
+    a.cls = plan.qd[0].cls;
+    a.items_per_query = plan.qd[0].items;
+    a.chunk = plan.cls.empty() ? 64u : (uint32_t)plan.cls[0].chunk;
+    a.scratch_off = 0;
+    const int sblocks = (int)std::min<uint64_t>(1024, (m + 255) / 256);
+    hipLaunchKernelGGL(noalloc_setup_kernel, dim3(std::max(sblocks, 1)), dim3(256), 0, stream, a);
+    HIPCHK(hipGetLastError());
+
+    g_last.ws = nullptr;
+    g_last.device = dev;
+    g_last.ctr = pl.ctr;
+    g_last.qs = pl.qs;
+    g_last.nq = (int)m;
+    g_last.timing = 0;
+    return enqueue(plan, pl, o, stream, nullptr, false);
+}
+
 // Deterministic synthetic points for the autotuner: sums of four uniforms
 // from a 64-bit LCG, centred and scaled (plumbing only, no depth arithmetic).
 void synth(std::vector<double>& v, size_t count, uint64_t seed) {
@@ -677,6 +882,22 @@ td_status td_depth_batched(const td_problem* probs, int32_t num, const td_option
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return TD_ERR_NO_DEVICE;
     return run(pv.data(), num, o, (hipStream_t)stream, true);
+}
+
+td_status td_depth_noalloc(const double* X, int64_t n, int32_t p, const double* Z, int64_t m, int32_t* counts,
+                           const td_options* opt, void* stream) {
+    td_options o = opt ? *opt : defaults();
+    td_status st = check_options(o);
+    if (st != TD_OK) return st;
+    Problem pr{X, n, p, Z, m, counts};
+    st = check_problem(pr);
+    if (st != TD_OK) return st;
+    if (m == 0) return TD_OK;
+    if (m > (int64_t)1 << 30) return TD_ERR_TOO_LARGE;
+    std::lock_guard<std::mutex> lk(g_mu);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return TD_ERR_NO_DEVICE;
+    return run_noalloc(pr, o, (hipStream_t)stream);
 }
 
 td_status td_get_stats(td_stats* out) {
@@ -811,6 +1032,7 @@ const char* td_status_string(td_status s) {
         case TD_ERR_HIP: return "HIP runtime error";
         case TD_ERR_DEVICE_STATUS: return "some queries failed (see device_status)";
         case TD_ERR_NO_DEVICE: return "no HIP device";
+        case TD_ERR_TOO_LARGE: return "call needs more than the static workspace of td_depth_noalloc";
     }
     return "unknown status";
 }

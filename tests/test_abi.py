@@ -50,7 +50,7 @@ def test_struct_layouts_match_header(tmp_path):
 
 
 def test_status_strings_and_version(lib):
-    for code in range(7):
+    for code in range(8):
         assert lib.td_status_string(code)
     assert lib.td_version() >= 1
 
