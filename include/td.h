@@ -95,10 +95,12 @@ typedef struct {
                                   down to 64 while there are fewer than four items per
                                   resident wave) */
     int32_t grid_blocks;       /* persistent blocks, 0 = auto */
-    double filter_scale;       /* scales the float32 error radius: 1 normal,
-                                  +inf re-checks every float32 decision,
-                                  0 trusts float32 blindly (negative control,
-                                  results may be wrong) */
+    double filter_scale;       /* scales the float32 error radius (error
+                                  and rounding terms): 1 normal, above 1
+                                  wider (still exact), +inf re-checks every
+                                  float32 decision, 0 trusts float32 with
+                                  no margin (negative control, results may
+                                  be wrong) */
     int32_t force_exact;       /* 1: every subset goes through the exact tier */
     int32_t timing;            /* 1: record HIP events per stage (td_get_stats) */
     int64_t deferred_capacity; /* max deferred subsets per call, 0 = default */

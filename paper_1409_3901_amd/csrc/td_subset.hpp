@@ -219,6 +219,10 @@ __device__ int sweep_filt(const float (&xr)[K][P], const SlotFilt<P>& S,
 #pragma unroll
     for (int c = 0; c < KS; ++c) mem[c] = uni(S.mem[c]);
     const float beta = unif(S.beta32 * fc.fscale);
+    // rounding of t' (8 u32) and truncation (4 quanta), scaled with the
+    // filter: none at a filter scale of 0 (negative control)
+    const float r8 = unif(8.0f * kU32 * fc.fscale);
+    const uint32_t rpad = fc.fscale > 0.0f ? 4u : 0u;
     uint32_t key[K];
     int nplus = 0;
     uint32_t weak = 0;   // points whose float32 key is not certified
@@ -248,11 +252,11 @@ __device__ int sweep_filt(const float (&xr)[K][P], const SlotFilt<P>& S,
         // hardware reciprocals are within 1 ulp: covered by the 8 u32 term
         // and the factor 1.001
         const float t = h2 * __builtin_amdgcn_rcpf(s) + 1.0f;
-        const float r = eps * __builtin_amdgcn_rcpf(s - 2.0f * eps) * 1.001f + 8.0f * kU32;
+        const float r = eps * __builtin_amdgcn_rcpf(s - 2.0f * eps) * 1.001f + r8;
         const float rqf = r * qscalef;
         const bool ok = (h1 > eps) && (s > 4.0f * eps) && (rqf < (float)kRqMax);
         const uint32_t q = min((uint32_t)(t * qscalef), qmax);
-        const uint32_t rq = ok ? (uint32_t)rqf + 4u : 0u;
+        const uint32_t rq = ok ? (uint32_t)rqf + rpad : 0u;
         // idx < M always: the side entry of a point that is not swept is
         // written but never read
         side[idx] = (uint16_t)(rq | (pos ? 0u : kSideNeg));
@@ -445,14 +449,15 @@ __device__ int sweep_filt(const float (&xr)[K][P], const SlotFilt<P>& S,
 // angular order is taken at bucket granularity first (a counting sort by
 // pseudo-angle) and refined exactly only where the minimum may lie.
 //
-// Keys: t' in [0, 2] maps to q = t' QS + W - QS ... in quanta, q in
-// [W, (NB - 1) W], with NB buckets (M/8) of W = 2^SH quanta, SH = 24 while
-// NB W stays within 2^31 (a bucket index is then the top byte of a key, one
-// byte-select instruction), else 31 - log2 NB.  Every point
-// carries a certified interval [q - rq, q + rq] (rq < W / 4) that contains the
-// key of the exact frame, so a bucket boundary that no interval crosses is a
-// strict gap of the angular order, and the state there is a state of the
-// sweep.  Bucket word (LDS): bits 0-10 points folded with delta = -1, bits
+// Keys: t' in [0, 2] maps to q = t' QS + W in quanta, q in [W, (NB - 1) W],
+// with NB buckets (M/8, 64 or 128) of W = 2^16 quanta.  The float32 path
+// forms q as the float 2^23 + q, whose bit pattern is the integer
+// 0x4B000000 + q (one binade, unit spacing): the interval ends need no
+// float-to-integer conversion, and a bucket index is byte 2 of those bits
+// (one byte-select).  Every point carries a certified interval [lo, hi]
+// (hi - lo < W / 2) that contains the key of the exact frame, so a bucket
+// boundary that no interval crosses is a strict gap of the angular order, and
+// the state there is a state of the sweep.  Bucket word (LDS): bits 0-10 points folded with delta = -1, bits
 // 11-21 points with delta = +1 (counted by the bucket of the interval's lower
 // end), bits 22-31 points whose interval crosses into the next bucket.
 //
@@ -469,10 +474,14 @@ constexpr uint32_t kHistStr = 1u << 22;
 constexpr uint32_t kAuxNeg = 1u << 31;
 constexpr int kListMax = 128;   // gathered points of the runs walked exactly
 // Key of a point that is not swept (padding, a member of I, or a point float64
-// cannot place): q - rq then lies in [2^31, 2^32), so its histogram word falls
-// past the NB buckets (the histogram holds 2^(32 - SH) words, and the scan
-// reads only the first NB).
+// cannot place): byte 2 of its lower end is 255, a histogram word past the NB
+// buckets (the histogram holds 256 words, and the scan reads only the first
+// NB).
 constexpr uint32_t kKeyOut = 0xffffffffu;
+// Bits of the float 2^23: key bits = kKeyBias + q for q in [0, 2^23).
+constexpr uint32_t kKeyBias = 0x4B000000u;
+// Histogram word of a key's lower-end bits.
+__device__ __forceinline__ uint32_t key_bucket(uint32_t bits) { return (bits >> 16) & 0xffu; }
 
 // Buckets per lane: an eighth of the points per lane (about eight points per
 // bucket).  The bounds L and U only decide when a sweep must be walked in
@@ -490,21 +499,23 @@ template <int K>
 struct BucketGeom {
     static constexpr int NBL = buckets_per_lane<K>();
     static constexpr int NB = 64 * NBL;
-    static constexpr int LOGNB = 6 + (NBL >= 2) + (NBL >= 4) + (NBL >= 8) + (NBL >= 16);
-    static constexpr int SH = LOGNB <= 7 ? 24 : 31 - LOGNB;
-    static constexpr int HW = 1 << (32 - SH);   // histogram words
+    static constexpr int SH = 16;
+    static constexpr int HW = 256;              // histogram words (byte 2 of a key)
     static constexpr uint32_t W = 1u << SH;
     static constexpr double QS = (double)(NB - 2) * (double)W / 2.0;   // quanta per unit of t'
+    static constexpr double QB = QS + (double)W;                        // q at t' = 1
     static constexpr uint32_t RQMAX = W / 4;
     // b = 4 eps / s below which a key radius passes the RQMAX check
     static constexpr double BCAP = 4.0 * (double)RQMAX / QS;
-    static_assert((uint64_t)NB * W <= (1ull << 31), "keys and radii stay below 2^31");
-    static_assert(HW >= NB + 64, "a word per lane past the buckets");
+    static_assert((uint64_t)NB * W <= (1ull << 23), "keys stay in the binade [2^23, 2^24)");
+    static_assert(NB <= 128 && HW >= NB + 64, "words of the lanes' uncertified keys past the buckets");
 };
 
-// float64 key of a point in bucket quanta; false if not certified
+// float64 key of a point in bucket quanta: the bits of its interval's lower
+// end (kKeyBias + q - rq) and the interval's width 2 rq with the fold bit;
+// false if not certified
 template <int K>
-__device__ __forceinline__ bool bucket_key64(double d1, double d2, double eps64, uint32_t& q, uint32_t& aux) {
+__device__ __forceinline__ bool bucket_key64(double d1, double d2, double eps64, uint32_t& lo, uint32_t& aux) {
     using G = BucketGeom<K>;
     double t, r;
     bool pos;
@@ -512,29 +523,34 @@ __device__ __forceinline__ bool bucket_key64(double d1, double d2, double eps64,
     const double rqd = r * G::QS;
     if (!(rqd < (double)(G::RQMAX - 4))) return false;
     // t' = t in [0, 2]: q = (t - 1) QS + QS + W
-    q = (uint32_t)(t * G::QS + (double)G::W);
-    aux = ((uint32_t)rqd + 2u) | (pos ? 0u : kAuxNeg);
+    const uint32_t q = (uint32_t)(t * G::QS + (double)G::W);
+    const uint32_t rq = (uint32_t)rqd + 2u;
+    lo = kKeyBias + q - rq;
+    aux = (2u * rq) | (pos ? 0u : kAuxNeg);
     return true;
 }
 
 // Float32 key of one point for the bucketed sweep: projection on (e1, e2),
 // fold by the sign of the first coordinate, pseudo-angle
-// t' = h2 / (h1 + |h2|) + 1 in bucket quanta, and its radius.  With eps the
+// t' = h2 / (h1 + |h2|) + 1 in bucket quanta, and its interval: the bits lo,
+// hi of the floats 2^23 + q -+ r.  With eps the
 // float32 error of each coordinate and a = eps / s <= 1/4 (from h1 > 4 eps),
 // the key moves by at most eps / (s - 2 eps) = a / (1 - 2a) <= a + 4a^2 =
 // (b + b^2) / 4 with b = 4a.  A radius that passes the check has b < BCAP, so
 // b^2 < BCAP b and the linear bound b (1 + BCAP) / 4 covers it; 8 u32 covers
 // the rounding of t' (hardware reciprocal within 1 ulp) and of the scaling to
-// quanta, 2 quanta the truncations (Algorithm 2, Step 1(b)).  Returns whether
-// the fold and the key are certified.  Contraction is off, so every
-// evaluation of a point gives the same bits.
+// quanta, 2 quanta the roundings of 2^23 + q and of its sum and difference
+// with the radius (half a quantum each: unit spacing in that binade)
+// (Algorithm 2, Step 1(b)).  Returns whether the fold and the key are
+// certified.  Contraction is off, so every evaluation of a point gives the
+// same bits.
 template <int P, int K>
 __device__ __forceinline__ bool key32(const float (&x)[P], const float (&f1)[P], const float (&f2)[P], float eps4,
-                                      float eR, uint32_t& q, uint32_t& rq, bool& pos) {
+                                      float eR, float eC, uint32_t& lo, uint32_t& hi, bool& pos) {
 #pragma clang fp contract(off)
     using G = BucketGeom<K>;
     const float QSf = (float)G::QS;
-    const float QBf = (float)(G::QS + (double)G::W);
+    const float QBf = (float)(G::QB + 8388608.0);   // 2^23 + q at t' = 1, exact
     float y1 = 0.0f, y2 = 0.0f;
 #pragma unroll
     for (int c = 0; c < P; ++c) {
@@ -547,33 +563,25 @@ __device__ __forceinline__ bool key32(const float (&x)[P], const float (&f1)[P],
     const float s = ay1 + fabsf(h2);
     const float rs = __builtin_amdgcn_rcpf(s);
     const float u = h2 * rs;
-    // b RQS with b = eps4 / s, as rs (eps4 RQS)
-    const float rqf = fmaf(rs, eR, 8.0f * kU32 * QSf + 2.0f);
-    q = (uint32_t)fmaf(u, QSf, QBf);
-    rq = (uint32_t)rqf;   // meaningful only when the key is certified
+    // b RQS with b = eps4 / s, as rs (eps4 RQS), plus eC = 8 u32 QS + 2
+    // quanta for the roundings
+    const float rqf = fmaf(rs, eR, eC);
+    const float Q = fmaf(u, QSf, QBf);
+    // meaningful only when the key is certified: then both ends stay in the
+    // binade [2^23, 2^24), where the bits grow with the value
+    lo = __float_as_uint(Q - rqf);
+    hi = __float_as_uint(Q + rqf);
     return (ay1 > eps4) && (rqf < (float)(G::RQMAX - 4));
 }
 
-// Histogram add of a float32 key that may be uncertified (ok false): such a
-// point takes the lane's own word past the buckets (the words past NB are
-// never read).
-template <int K>
-__device__ __forceinline__ void hist_add32(uint32_t* hist, uint32_t q, uint32_t rq, bool pos, bool ok, uint32_t out_lo) {
-    using G = BucketGeom<K>;
-    const uint32_t lo = ok ? q - rq : out_lo;
-    const uint32_t blo = lo >> G::SH;
-    const uint32_t inc = (pos ? kHistPos : kHistNeg) | ((((q + rq) >> G::SH) - blo) << 22);
-    atomicAdd(&hist[blo], inc);
-}
-
-// Histogram add of a key from the float64 re-check: a point that is not
-// swept (key kKeyOut) adds to one of the NB words past the buckets.
-template <int K>
-__device__ __forceinline__ void hist_add(uint32_t* hist, uint32_t q, uint32_t rq, bool pos) {
-    using G = BucketGeom<K>;
-    const uint32_t blo = (q - rq) >> G::SH;
-    // crossing count field: 1 when the interval ends in the next bucket
-    const uint32_t inc = (pos ? kHistPos : kHistNeg) | ((((q + rq) >> G::SH) - blo) << 22);
+// Histogram add of a key interval [lo, hi] (bits) that may be uncertified
+// (ok false): such a point takes the lane's own word past the buckets, and a
+// point that float64 cannot place either (lo = kKeyOut) the word 255 (the
+// words past NB are never read).  The crossing count field is 1 when the
+// interval ends in the next bucket.
+__device__ __forceinline__ void hist_add32(uint32_t* hist, uint32_t lo, uint32_t hi, bool pos, bool ok, uint32_t out_lo) {
+    const uint32_t blo = key_bucket(ok ? lo : out_lo);
+    const uint32_t inc = (pos ? kHistPos : kHistNeg) | ((key_bucket(hi) - blo) << 22);
     atomicAdd(&hist[blo], inc);
 }
 
@@ -599,6 +607,10 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     const float eps4 = unif(4.0f * S.beta32 * fc.fscale);
     // eps4 times the quanta per unit of b = 4 eps / s in the linear radius bound
     const float eR = eps4 * (float)(G::QS * (1.001 / 4.0) * (1.0 + G::BCAP));
+    // quanta for the roundings of t' and of the scaling (8 u32 QS) and the
+    // truncations (2); scaled with the filter like the error term, so that a
+    // filter scale of 0 leaves no margin at all (negative control)
+    const float eC = unif((8.0f * kU32 * (float)G::QS + 2.0f) * fc.fscale);
     // Keys and histogram in one pass; the keys are not kept: the rare walk
     // evaluates them again.  Points float32 cannot certify are re-checked in
     // float64 below and keep their keys in the staging arrays.
@@ -606,14 +618,14 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     // the error bound of 0, so they never pass the key check and are left out
     // like every other point that fails it.
     // Padding rows past nnz are zero and fail the key check too.  A point
-    // that fails it adds to the word HW - 1 - lane, past the buckets.
-    const uint32_t out_lo = 0xffffffffu - ((uint32_t)lane << G::SH);
+    // that fails it adds to the word 128 + lane, past the buckets.
+    const uint32_t out_lo = (128u + (uint32_t)lane) << 16;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        uint32_t q, rq;
+        uint32_t lo, hi;
         bool pos;
-        const bool ok = key32<P, K>(xr[i], f1, f2, eps4, eR, q, rq, pos);
-        hist_add32<K>(hist, q, rq, pos, ok, out_lo);
+        const bool ok = key32<P, K>(xr[i], f1, f2, eps4, eR, eC, lo, hi, pos);
+        hist_add32(hist, lo, hi, pos, ok, out_lo);
     }
     __syncthreads();
     // totals of the lane's NBL buckets [lane NBL, lane NBL + NBL) and of the
@@ -657,9 +669,9 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
             bool valid = idx < nnz;
 #pragma unroll
             for (int c = 0; c < KS; ++c) valid = valid && (idx != mem[c]);
-            uint32_t q, rq;
+            uint32_t lo, hi;
             bool pos;
-            const bool ok = key32<P, K>(xr[i], f1, f2, eps4r, eR, q, rq, pos);
+            const bool ok = key32<P, K>(xr[i], f1, f2, eps4r, eR, eC, lo, hi, pos);
             weak |= (valid && !ok) ? (1u << i) : 0u;
         }
         uint32_t lost = 0;
@@ -670,15 +682,15 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
             ++rechecks;
             double d1, d2;
             fp64_point<P>(fc.x64, S64.e1, S64.e2, idx, d1, d2);
-            uint32_t q2, a2;
-            if (!bucket_key64<K>(d1, d2, S64.beta64 * (double)fc.nrm[idx], q2, a2)) {
-                q2 = kKeyOut;
+            uint32_t lo2, a2;
+            if (!bucket_key64<K>(d1, d2, S64.beta64 * (double)fc.nrm[idx], lo2, a2)) {
+                lo2 = kKeyOut;
                 a2 = 0u;
                 lost |= 1u << i;
             }
-            wq[i] = q2;
+            wq[i] = lo2;
             wa[i] = (int)a2;
-            hist_add<K>(hist, q2, a2 & 0x7fffffffu, !(a2 & kAuxNeg));
+            hist_add32(hist, lo2, lo2 + (a2 & 0x7fffffffu), !(a2 & kAuxNeg), true, 0u);
         }
         partial = __any(lost != 0);
         __syncthreads();
@@ -764,6 +776,7 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     for (int i = 0; i < K; ++i) {
         // the same keys as the histogram's: float32 again, or the float64
         // re-check's from the staging arrays
+        // qk: bits of the interval's lower end, aux: its width and the fold
         if ((weak >> i) & 1u) {
             qk[i] = wq[i];
             aux[i] = (uint32_t)wa[i];
@@ -772,14 +785,13 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
             bool valid = idx < nnz;
 #pragma unroll
             for (int c = 0; c < KS; ++c) valid = valid && (idx != mem[c]);
-            uint32_t q, rq;
+            uint32_t lo, hi;
             bool pos;
-            const bool ok = key32<P, K>(xr[i], f1, f2, eps4w, eR, q, rq, pos);
-            qk[i] = (valid && ok) ? q : kKeyOut;
-            aux[i] = (rq & 0x7fffffffu) | (pos ? 0u : kAuxNeg);
+            const bool ok = key32<P, K>(xr[i], f1, f2, eps4w, eR, eC, lo, hi, pos);
+            qk[i] = (valid && ok) ? lo : kKeyOut;
+            aux[i] = ((hi - lo) & 0x7fffffffu) | (pos ? 0u : kAuxNeg);
         }
-        const uint32_t rq = aux[i] & 0x7fffffffu;
-        const uint32_t blo = ((qk[i] - rq) >> G::SH) & (NB - 1);
+        const uint32_t blo = key_bucket(qk[i]) & (NB - 1);
         const uint32_t ri = hist[blo] & 0x7fffffffu;
         rinf[i] = ri;
         const bool g = (qk[i] != kKeyOut) && (hist[(ri >> 11) & (NB - 1)] >> 31);
@@ -801,8 +813,7 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
 #pragma unroll
         for (int i = 0; i < K; ++i)
             if ((gm >> i) & 1u) {
-                // lower end of the interval (q >= W > rq for a placed point)
-                list[k] = make_uint4(qk[i] - (aux[i] & 0x7fffffffu), aux[i], rinf[i], (uint32_t)(lane * K + i));
+                list[k] = make_uint4(qk[i], aux[i], rinf[i], (uint32_t)(lane * K + i));
                 ++k;
             }
     }
@@ -847,14 +858,14 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
                 // cluster: maximal run of overlapping intervals, with the
                 // count of its positive-fold points
                 const uint4 va = nx;
-                uint32_t mhi = va.x + 2u * (va.y & 0x7fffffffu);   // upper end
+                uint32_t mhi = va.x + (va.y & 0x7fffffffu);   // upper end
                 int npos_c = (va.y & kAuxNeg) ? 0 : 1;
                 int b = a;
                 nx = (b + 1 < gtot) ? list[b + 1] : kNone;
 #pragma unroll 1
                 while (b + 1 < gtot && (nx.z >> 11) == run && nx.x <= mhi) {
                     ++b;
-                    mhi = max(mhi, nx.x + 2u * (nx.y & 0x7fffffffu));
+                    mhi = max(mhi, nx.x + (nx.y & 0x7fffffffu));
                     npos_c += (nx.y & kAuxNeg) ? 0 : 1;
                     nx = (b + 1 < gtot) ? list[b + 1] : kNone;
                 }
