@@ -92,6 +92,9 @@ def main():
     ap.add_argument("--paper-grid", action="store_true",
                     help="the paper's simulation grid (X ~ N(0, I_p), z = 0, one query), "
                          "timed per query beside the paper's own timings as context")
+    ap.add_argument("--p2", action="store_true",
+                    help="p = 2, n = 1024, m = 1024 queries: one sweep per query (Algorithm 2 "
+                         "alone), filtered and plain tiers, against stored oracle counts")
     ap.add_argument("--every-point", action="store_true",
                     help="the depth of every observation of a sample (the paper's real-data "
                          "shapes on seeded stand-ins), timed per observation beside the "
@@ -127,6 +130,8 @@ def main():
         return bench_paper_grid(td, workloads, torch, np, dev)
     if a.every_point:
         return bench_every_point(td, workloads, torch, np, dev)
+    if a.p2:
+        return bench_p2(a, td, workloads, torch, np, dev)
     if a.all_configs:
         return bench_all_configs(td, workloads, torch, np, dev)
     X, Z = workloads.c3()
@@ -233,6 +238,59 @@ def main():
     if not a.no_cpu:
         res["cpu_baseline"] = cpu_baseline(X, Z, a.cpu_seconds)
     print(json.dumps(res), flush=True)
+
+
+def bench_p2(a, td, workloads, torch, np, dev):
+    """p = 2 (one sweep per query, I empty): n = 1024 points, m = 1024
+    queries, one td_depth call per step (HIP events around the call, mean over
+    the timed steps), filtered and plain tiers, mismatches against the stored
+    oracle counts, and the roofline of the subset kernel (algorithmic
+    lane-ops of the sweeps over its duration)."""
+    X, Z = workloads.p2()
+    n, p = X.shape
+    m = Z.shape[0]
+    n0 = [int(np.sum(np.all(X == Z[q], axis=1))) for q in range(m)]
+    ops = sum(algorithmic_ops(n - n0[q], p) for q in range(m))
+    g = _stored_counts("p2")
+    exp = np.array([g[str(q)] for q in range(m)])
+    Xd = torch.from_numpy(X).to(dev)
+    Zd = torch.from_numpy(Z).to(dev)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for prec, opts in (("filtered", {}), ("plain", {"precision": "plain"})):
+        for _ in range(a.warmup):
+            td.depth(Xd, Zd, timing=True, **opts)
+        torch.cuda.synchronize()
+        tot, sub = 0.0, 0.0
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        for _ in range(a.steps):
+            t0.record(stream)
+            c = td.depth(Xd, Zd, timing=True, **opts)
+            t1.record(stream)
+            torch.cuda.synchronize()
+            tot += t0.elapsed_time(t1)
+            st = td.get_stats()
+            sub += st["subset_ms"]
+        ms, sub_ms = tot / a.steps, sub / a.steps
+        got = c.cpu().numpy()
+        achieved = ops / (sub_ms / 1e3) / 1e12
+        out[prec] = {"ms_per_step": ms, "queries_per_s": m / (ms / 1e3), "sweeps_per_s": m / (ms / 1e3),
+                     "mismatches_vs_oracle": int(np.sum(got != exp)), "queries_checked": m,
+                     "deferred_subsets": st["deferred_subsets"], "device_status": st["device_status"],
+                     "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
+                                  "frac": achieved / PEAK_VALU_TOPS, "traffic": None,
+                                  "kernel": "subset_kernel<2,16,%d>" % (3 if prec == "filtered" else 0),
+                                  "kernel_ms": sub_ms, "ops_per_launch": ops}}
+    f = out["filtered"]
+    print(json.dumps({"metric": "queries/s at p=2, n=1024 (one sweep per query)", "value": f["queries_per_s"],
+                      "unit": "queries/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+                      "ms_per_step": f["ms_per_step"], "higher_is_better": True, "dtype": "f32",
+                      "data": "synthetic",
+                      "config": {"workload": "p2: N(0,I_2), n=1024, m=1024 queries (512 sample points, "
+                                             "512 N(0,I_2))"},
+                      "filtered": f, "plain_fp64": out["plain"],
+                      "speedup_filtered_vs_plain": out["plain"]["ms_per_step"] / f["ms_per_step"]}), flush=True)
 
 
 def bench_c4(a, td, workloads, torch, np, dev):

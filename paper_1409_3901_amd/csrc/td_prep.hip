@@ -170,8 +170,10 @@ __global__ __launch_bounds__(256) void prep_kernel(Pools pl) {
         // is within e = (p + 4) u32 of the sign-deciding <u, x_i / ||x_i||>.
         // A point within e of a side is counted on it, so a count can only be
         // too high and the bound stays valid.
+        // (p >= 3 only: at p = 2 a query has one sweep, cheaper than the
+        // n'^2 p products of the bound)
         int ub = 0x7fffffff;
-        if (pl.prune && p >= 2 && nnz > 0) {
+        if (pl.prune && p >= 3 && nnz > 0) {
             __syncthreads();
             for (int k = tid; k < nnz * p; k += blockDim.x) s_x[k] = x32[k];
             __syncthreads();

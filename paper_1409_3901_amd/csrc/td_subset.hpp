@@ -999,7 +999,10 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
     using Slot = typename SlotOf<P, TIER>::type;
     __shared__ Slot slots[64];
     constexpr bool BUCKET = TIER == kFiltBucket;
-    __shared__ uint16_t side[TIER == kFilt ? M : 1];
+    // side table of the full-sort sweep: the bitonic tier, and the bucketed
+    // kernels of p = 2, which sort in full what the buckets cannot finish
+    constexpr bool FULLSORT = TIER == kFilt || (BUCKET && P == 2);
+    __shared__ uint16_t side[FULLSORT ? M : 1];
     __shared__ uint32_t hist[BUCKET ? BucketGeom<K>::HW : 1];
     __shared__ uint4 glist[BUCKET ? kListMax : 1];
     // per-block device scratch: float64 basis slots, then the staging arrays
@@ -1149,15 +1152,23 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
                         term = kDefer;
                     } else {
                         if constexpr (BUCKET) {
-                            // bucket words count at most 1023 points per field;
-                            // what the bucketed sweep cannot finish goes to the
-                            // exact tier
-                            term = kDefer;
+                            // bucket words count at most 1023 points per field
+                            // (p = 2 with 1024 points in the sweep), and a walk
+                            // gathers at most kListMax points: at p = 2 (one
+                            // sweep per query) the full bitonic sort takes
+                            // these sweeps, otherwise the exact tier does
+                            term = kFallback;
                             if (nnz - KS <= 1023)
                                 term = sweep_bucket<P, K>(xf, reinterpret_cast<const SlotFilt<P>&>(S), slots64[s],
                                                           nnz, fc, hist, glist, sg, min(qbest, wbest), rechecks,
                                                           nwalked);
-                            if (term == kFallback) term = kDefer;
+                            if (term == kFallback) {
+                                if constexpr (P == 2)
+                                    term = sweep_filt<P, K>(xf, reinterpret_cast<const SlotFilt<P>&>(S), slots64[s],
+                                                            nnz, fc, side, sg, rechecks);
+                                else
+                                    term = kDefer;
+                            }
                         } else {
                             term = sweep_filt<P, K>(xf, reinterpret_cast<const SlotFilt<P>&>(S), slots64[s], nnz,
                                                     fc, side, sg, rechecks);

@@ -5,7 +5,7 @@ inputs of ``workloads``; nothing is taken from the HIP path.  The script is
 resumable: each finished query is saved at once, and queries already present
 are skipped.
 
-    python tests/golden/make_golden.py [c1 c2 c3 c5 c4] [--threads T]
+    python tests/golden/make_golden.py [c1 c2 c3 c5 c4 p2] [--threads T]
     python tests/golden/make_golden.py c5 --queries 15,14,13 --part b
     python tests/golden/make_golden.py c4wide wide
 
@@ -42,7 +42,7 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 import workloads  # noqa: E402
 
-SEEDS = {"c1": 0, "c2": 2, "c3": 3, "c4": 4, "c5": 5}
+SEEDS = {"c1": 0, "c2": 2, "c3": 3, "c4": 4, "c5": 5, "p2": 7}
 C4_BUDGET = 3.0e8
 # (dataset, query) of c4 at p = 5 above the budget: n = 517, 518 (10 points
 # per lane), 642, 644 (12), 770, 773 (14).

@@ -28,6 +28,9 @@ headline configurations of this project):
            2^40, so the map is exact in float64 and exact ties survive; about
            30% of centred coordinates exceed 2^24, so float32 rounding is
            real.
+* ``p2`` : p=2, n=1024 points from N(0, I_2), m=1024 queries (512 sample
+           points, 512 from N(0, I_2)): one sweep of 1023 or 1024 points per
+           query (Algorithm 2 on its own).
 * ``grid``: the paper's speed-comparison design: N(0, I_p), z = alpha * 1_p.
 * ``observations``: the depth of every observation (queries = the sample) on
            seeded stand-ins with the shapes of the paper's two real data sets
@@ -47,7 +50,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = [
-    "c1", "c2", "c3", "c4", "c5", "grid", "observations", "config",
+    "c1", "c2", "c3", "c4", "c5", "p2", "grid", "observations", "config",
     "lattice_small", "ray_duplicated", "rank_deficient", "near_degenerate",
     "symmetric", "duplicated", "outside_hull_query", "unimodular", "wide",
     "WIDE_CASES",
@@ -104,6 +107,14 @@ def c4(seed: int = 4, num: int = 256, queries: int = 8):
             Z = rng.uniform(-1.0, 1.0, size=(queries, p))
         out.append((_f64(X), _f64(Z)))
     return out
+
+
+def p2(seed: int = 7):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((1024, 2))
+    idx = rng.choice(1024, 512, replace=False)
+    Z = np.vstack([X[idx], rng.standard_normal((512, 2))])
+    return _f64(X), _f64(Z)
 
 
 def unimodular(rng, p: int, steps: int = 12):
@@ -270,6 +281,8 @@ def config(name: str):
         return c5()
     if name == "c4":
         return c4()
+    if name == "p2":
+        return p2()
     raise KeyError(name)
 
 
