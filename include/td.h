@@ -88,6 +88,25 @@ typedef enum {
     TD_SWEEP_BITONIC = 1  /* full bitonic sort of every sweep */
 } td_sweep;
 
+/* Which of the paper's algorithms computes the count (td_depth, td_depth_ex
+ * only; td_depth_batched and td_depth_noalloc return TD_ERR_UNSUPPORTED for
+ * ADIA). */
+typedef enum {
+    TD_METHOD_RCOM = 0,   /* Algorithm 1 with Algorithm 2 (Section 3): every
+                             (p-2)-subset; the exact count */
+    TD_METHOD_ADIA = 1    /* Algorithm 3 (Section 4): a descent over critical
+                             (p-1)-sets by Proposition 3 (Steps 2-4), then
+                             Algorithm 1 over the subsets of the candidate
+                             points only (Step 5), swept by the certified
+                             tiers.  The paper reports the exact count in all
+                             its experiments but proves no bound; the result
+                             is a count attained by some subset, so it never
+                             lies below the depth, and it equals the depth
+                             whenever an optimal subset lies among the
+                             candidates.  For p < 3 or n <= 2p, Algorithm 1
+                             (the paper's advice). */
+} td_method;
+
 typedef struct {
     int32_t precision;         /* td_precision (default TD_PREC_FP32_FILTERED) */
     int32_t autotune;          /* 1: use the tuned launch shape when cached */
@@ -115,6 +134,7 @@ typedef struct {
                                   is reached; 0: sweep every subset.  The
                                   counts are the same either way.  Ignored by
                                   TD_PREC_FP64_PLAIN. */
+    int32_t method;            /* td_method (default TD_METHOD_RCOM) */
 } td_options;
 
 typedef struct {
@@ -134,6 +154,10 @@ typedef struct {
     uint64_t exact_subsets;      /* deferred subsets the exact tier took up:
                                     each deferred subset once, so this equals
                                     min(deferred_subsets, deferred_capacity) */
+    uint64_t adia_evaluations;   /* TD_METHOD_ADIA: subsets evaluated in the
+                                    descent (Algorithm 3, Steps 2-4) */
+    uint64_t adia_candidates;    /* TD_METHOD_ADIA: candidate points of Step 5,
+                                    summed over the queries */
 } td_stats;
 
 /* One independent depth problem of a batch (pointers as for td_depth). */

@@ -6,6 +6,8 @@ its Python binding) never imports, loads or calls anything here.
 
 * ``depth_counts`` -- the paper's first algorithm made exact (C++/OpenMP,
   ``td_oracle.cpp``): the arbiter at workload scale.
+* ``depth_adia``   -- the paper's adaptive algorithm (Algorithm 3), step by
+  step, with exact subset values.
 * ``depth_range``  -- the same loop restricted to a range of subset ranks (a
   bounded sample, used to time the oracle).
 * ``depth_vertex`` -- the critical-direction route in C++ (tiny inputs).
@@ -61,6 +63,9 @@ def _load():
     lib.oracle_depth_vertex.restype = ctypes.c_int
     lib.oracle_binom.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.oracle_binom.restype = ctypes.c_uint64
+    lib.oracle_depth_adia.argtypes = [dp, ctypes.c_int64, ctypes.c_int32, dp, ctypes.c_int64, i64p, i64p,
+                                      ctypes.c_int32, ctypes.c_int32]
+    lib.oracle_depth_adia.restype = ctypes.c_int
     lib.oracle_enumerate.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64,
                                      ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]
     lib.oracle_enumerate.restype = ctypes.c_int64
@@ -108,6 +113,24 @@ def depth_range(X, z, r0: int, r1: int, threads: int | None = None, exact_only: 
     if rc != 0:
         raise ValueError("oracle_depth_range failed with code %d" % rc)
     return int(out.value), int(sw.value)
+
+
+def depth_adia(X, Z, threads: int | None = None, exact_only: bool = False):
+    """Depth counts by the paper's adaptive algorithm (Algorithm 3) and the
+    number of Step 5 candidate points per query (-1: Algorithm 1 was used)."""
+    lib = _load()
+    X, Xp = _arr(X)
+    Z, Zp = _arr(np.atleast_2d(Z))
+    n, p = X.shape
+    m = Z.shape[0]
+    out = np.zeros(m, dtype=np.int64)
+    ks = np.zeros(m, dtype=np.int64)
+    i64 = ctypes.POINTER(ctypes.c_int64)
+    rc = lib.oracle_depth_adia(Xp, n, p, Zp, m, out.ctypes.data_as(i64), ks.ctypes.data_as(i64),
+                               int(threads or default_threads()), EXACT_ONLY if exact_only else 0)
+    if rc != 0:
+        raise ValueError("oracle_depth_adia failed with code %d" % rc)
+    return out, ks
 
 
 def depth_vertex(X, z) -> int:

@@ -53,6 +53,8 @@
  */
 #include <algorithm>
 #include <cmath>
+#include <deque>
+#include <map>
 #include <cstdint>
 #include <cstring>
 #include <limits>
@@ -411,7 +413,11 @@ struct Ctx {
 };
 
 // Returns delta_I + b_I for the subset `I`, or -1 if the subset is invalid.
-int subset_term(const Ctx& C, const std::vector<int>& I) {
+// If `argmin` is given, it receives the points (indices, ascending) of the
+// runs of equal angle next to a state of the sweep where min(S, m - S) = b_I:
+// the points that, with I, span a critical hyperplane attaining b_I
+// (Algorithm 3, Steps 2(c) and 4(a)(ii)).
+int subset_term(const Ctx& C, const std::vector<int>& I, std::vector<int>* argmin = nullptr) {
     const PointSet& P = *C.P;
     const int p = P.p, k = p - 2;
     const bool xo = C.exact_only;
@@ -591,10 +597,39 @@ int subset_term(const Ctx& C, const std::vector<int>& I) {
     int S = 0;
     for (auto& q : pts) if (q.sig > 0) ++S;
     int best = std::min(S, m - S);
+    const int S_start = S;
     for (size_t i = 0; i < order.size(); ++i) {
         S += -pts[order[i]].sig;
         bool run_end = (i + 1 == order.size()) || adj[i] != 0;
         if (run_end) best = std::min(best, std::min(S, m - S));
+    }
+    if (argmin) {
+        // runs of exactly equal angle; state r is the one after run r - 1
+        // (state 0 before the first run, state R after the last: both lie
+        // next to the last and the first run, the sweep being circular)
+        argmin->clear();
+        std::vector<int> run_of(order.size());
+        int R = 0;
+        for (size_t i = 0; i < order.size(); ++i) {
+            run_of[i] = R;
+            if ((i + 1 == order.size()) || adj[i] != 0) ++R;
+        }
+        std::vector<int> st((size_t)R + 1);
+        int Sr = S_start;
+        st[0] = Sr;
+        for (size_t i = 0; i < order.size(); ++i) {
+            Sr += -pts[order[i]].sig;
+            if ((i + 1 == order.size()) || adj[i] != 0) st[(size_t)run_of[i] + 1] = Sr;
+        }
+        std::vector<char> hot((size_t)R, 0);
+        for (int r = 0; r <= R && R > 0; ++r) {
+            if (std::min(st[(size_t)r], m - st[(size_t)r]) != best) continue;
+            if (r == 0 || r == R) { hot[(size_t)R - 1] = 1; hot[0] = 1; }
+            else { hot[(size_t)r - 1] = 1; hot[(size_t)r] = 1; }
+        }
+        for (size_t i = 0; i < order.size(); ++i)
+            if (hot[(size_t)run_of[i]]) argmin->push_back(pts[order[i]].idx);
+        std::sort(argmin->begin(), argmin->end());
     }
 
     // ---- depth of 0 inside span(x_I) among the points lying there
@@ -735,6 +770,176 @@ Prepared prepare(const double* X, int64_t n, int p, const double* z, bool exact_
     return R;
 }
 
+// ------------------------------------------------ Algorithm 3 (ADIA)
+// Exact sign of the inner product x_a . x_b of two centred points.
+int dot_sign(const PointSet& P, int a, int b, bool exact_only) {
+    const int p = P.p;
+    if (!exact_only) {
+        double v = 0.0, ab = 0.0;
+        for (int c = 0; c < p; ++c) {
+            v += P.fd(a)[c] * P.fd(b)[c];
+            ab += std::fabs(P.fd(a)[c] * P.fd(b)[c]);
+        }
+        const double N = (double)(2 * p + 4);
+        if (std::fabs(v) > ab * N * U64 / (1.0 - N * U64) * 1.0001) return v > 0 ? 1 : -1;
+    }
+    return dot_big(std::vector<Big>(P.ex(a), P.ex(a) + p), P.ex(b), p).sgn;
+}
+
+bool contains(const std::vector<int>& v, int x) { return std::find(v.begin(), v.end(), x) != v.end(); }
+
+std::vector<int> with(std::vector<int> v, int x) {
+    v.push_back(x);
+    std::sort(v.begin(), v.end());
+    return v;
+}
+
+std::vector<int> without(const std::vector<int>& v, size_t r) {
+    std::vector<int> w;
+    for (size_t i = 0; i < v.size(); ++i)
+        if (i != r) w.push_back(v[i]);
+    return w;
+}
+
+// Algorithm 3 (Section 4) on the centred nonzero points of one query, with
+// the counts of Algorithm 1 (a subset's value is delta_I + b_I, so that the
+// value of a critical (p-1)-set is that of the subset it came from).
+// Returns the ADIA value (without n0), or -1 where the algorithm does not
+// apply (p < 3, n' <= 2p, or no seed subset; the caller then uses
+// Algorithm 1, as the paper recommends for n <= 2p).  *ksize receives the
+// number of candidate points of Step 5.
+//
+// Readings: the popped node's (p-2)-subsets are taken in the order of the
+// element left out (first element first); new nodes are appended in
+// ascending order of the added point; the seed point x_{i_{p-1}} of Step 2(c)
+// is the smallest index next to a minimising state of the seed subset; the
+// side X_F of Step 5(a) is the closed side of F's hyperplane holding fewer
+// points (the side with det[x_F | x] <= 0 on a tie); Step 5's candidates
+// also hold the points of the subset that attained d0 in Step 4, so that its
+// value is one of those of Step 5(b).
+int adia_term(const PointSet& P, bool xo, int64_t* ksize) {
+    const int p = P.p, k = p - 2, n = P.n;
+    *ksize = -1;
+    if (p < 3 || n <= 2 * p) return -1;
+    Ctx C{&P, xo};
+    // Step 2(a): the direction among +-x_j with the fewest points on its
+    // closed negative side
+    int bestc = std::numeric_limits<int>::max(), bj = -1, bs = 0;
+    for (int j = 0; j < n; ++j) {
+        int cp = 0, cn = 0;   // #{x_j . x_i <= 0}, #{x_j . x_i >= 0}
+        for (int i = 0; i < n; ++i) {
+            const int d = dot_sign(P, j, i, xo);
+            if (d <= 0) ++cp;
+            if (d >= 0) ++cn;
+        }
+        if (cp < bestc) { bestc = cp; bj = j; bs = 1; }
+        if (cn < bestc) { bestc = cn; bj = j; bs = -1; }
+    }
+    // Step 2(b): order by u_min . x; the seed subset is the p - 2 points with
+    // the smallest nonnegative projections
+    std::vector<Big> pr((size_t)n);
+    int kneg = 0;
+    for (int i = 0; i < n; ++i) {
+        Big d = dot_big(std::vector<Big>(P.ex(bj), P.ex(bj) + p), P.ex(i), p);
+        pr[(size_t)i] = bs > 0 ? d : neg(d);
+        if (pr[(size_t)i].sgn < 0) ++kneg;
+    }
+    if (kneg == 0) { *ksize = 0; return 0; }   // no point strictly below: depth 0 (Step 6)
+    std::vector<int> nonneg;
+    for (int i = 0; i < n; ++i)
+        if (pr[(size_t)i].sgn >= 0) nonneg.push_back(i);
+    std::sort(nonneg.begin(), nonneg.end(), [&](int a, int b) {
+        const int c = sub(pr[(size_t)a], pr[(size_t)b]).sgn;
+        return c < 0 || (c == 0 && a < b);
+    });
+    if ((int)nonneg.size() < k) return -1;
+    std::vector<int> I0(nonneg.begin(), nonneg.begin() + k);
+    std::sort(I0.begin(), I0.end());
+    // Step 2(c): the seed critical set
+    std::vector<int> T;
+    const int t0 = subset_term(C, I0, &T);
+    if (t0 < 0) return -1;
+    int h = -1;
+    for (int v : T)
+        if (!contains(I0, v)) { h = v; break; }
+    if (h < 0) return -1;
+    // Step 3
+    std::map<std::vector<int>, int> Q;
+    std::deque<std::vector<int>> N;
+    const std::vector<int> C0 = with(I0, h);
+    Q[C0] = t0;
+    N.push_back(C0);
+    int d0 = t0;
+    std::vector<int> bestJ = I0;
+    // Step 4
+    while (!N.empty()) {
+        const std::vector<int> F = N.front();
+        N.pop_front();
+        for (size_t r = 0; r < F.size(); ++r) {
+            const std::vector<int> J = without(F, r);
+            std::vector<int> TJ;
+            const int dt = subset_term(C, J, &TJ);
+            if (dt < 0) continue;
+            for (int v : TJ) {
+                if (contains(F, v)) continue;
+                const std::vector<int> Nn = with(J, v);
+                if (!Q.count(Nn)) {
+                    Q[Nn] = dt;
+                    N.push_back(Nn);
+                }
+            }
+            if (d0 > dt) {
+                d0 = dt;
+                bestJ = J;
+                break;
+            }
+        }
+        for (auto it = Q.begin(); it != Q.end();) {
+            if (it->second > d0) it = Q.erase(it); else ++it;
+        }
+        std::deque<std::vector<int>> keep;
+        for (auto& e : N)
+            if (Q.count(e)) keep.push_back(e);
+        N.swap(keep);
+    }
+    // Step 5(a): candidate points, the closed smaller side of every remaining
+    // critical hyperplane
+    std::vector<char> inK((size_t)n, 0);
+    std::vector<int> rows((size_t)p);
+    for (int r = 0; r < p; ++r) rows[(size_t)r] = r;
+    for (const auto& e : Q) {
+        std::vector<int> sg((size_t)n);
+        int cneg = 0, cpos = 0;
+        for (int l = 0; l < n; ++l) {
+            std::vector<int> cols = e.first;
+            cols.push_back(l);
+            sg[(size_t)l] = contains(e.first, l) ? 0 : minor_sign(P, cols, rows, xo);
+            if (sg[(size_t)l] < 0) ++cneg;
+            if (sg[(size_t)l] > 0) ++cpos;
+        }
+        const int side = (cneg <= cpos) ? -1 : 1;
+        for (int l = 0; l < n; ++l)
+            if (sg[(size_t)l] == 0 || sg[(size_t)l] == side) inK[(size_t)l] = 1;
+    }
+    for (int v : bestJ) inK[(size_t)v] = 1;
+    std::vector<int> K;
+    for (int l = 0; l < n; ++l)
+        if (inK[(size_t)l]) K.push_back(l);
+    *ksize = (int64_t)K.size();
+    // Step 5(b): Algorithm 1 over the (p-2)-subsets of the candidates
+    const uint64_t total = binom((int)K.size(), k);
+    std::vector<int> best5((size_t)thread_slots(), std::numeric_limits<int>::max());
+    visit_range(0, total, (int)K.size(), k, 256, [&](int64_t, uint64_t, const std::vector<int>& pos) {
+        std::vector<int> I((size_t)k);
+        for (int c = 0; c < k; ++c) I[(size_t)c] = K[(size_t)pos[(size_t)c]];
+        const int t = subset_term(C, I);
+        const size_t w = (size_t)thread_slot();
+        if (t >= 0 && t < best5[w]) best5[w] = t;
+    });
+    for (int b : best5) d0 = std::min(d0, b);
+    return d0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -814,6 +1019,37 @@ int oracle_depth_vertex(const double* X, int64_t n, int32_t p, const double* z, 
 }
 
 uint64_t oracle_binom(int32_t n, int32_t k) { return binom(n, k); }
+
+// Depth counts by Algorithm 3 (ADIA, Section 4): out[q] = n0 + the ADIA
+// value, ksize[q] = the number of candidate points of its Step 5, or -1
+// where ADIA does not apply and Algorithm 1 gave the count.  The paper
+// assumes general position; the value is then the depth in the paper's
+// experiments, and in every case a value attained by some subset, hence
+// never below the depth.
+int oracle_depth_adia(const double* X, int64_t n, int32_t p, const double* Z, int64_t m, int64_t* out,
+                      int64_t* ksize, int32_t threads, int32_t flags) {
+    if (!X || !Z || !out || !ksize || n < 1 || p < 1 || m < 0) return 1;
+    for (int64_t i = 0; i < n * p; ++i) if (!std::isfinite(X[i])) return 2;
+    for (int64_t i = 0; i < m * p; ++i) if (!std::isfinite(Z[i])) return 2;
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#endif
+    const bool xo = (flags & ORACLE_EXACT_ONLY) != 0;
+    for (int64_t q = 0; q < m; ++q) {
+        Prepared R = prepare(X, n, p, Z + q * p, xo);
+        ksize[q] = -1;
+        if (R.kind == 1) { out[q] = R.n0 + R.value; continue; }
+        int v = -1;
+        if (R.P.p == p) v = adia_term(R.P, xo, &ksize[q]);
+        if (v < 0) {
+            Ctx C{&R.P, xo};
+            v = min_over_range(C, 0, binom(R.P.n, R.P.p - 2), nullptr);
+            ksize[q] = -1;
+        }
+        out[q] = R.n0 + v;
+    }
+    return 0;
+}
 
 // The k-subsets of {0..n-1} of lexicographic rank [r0, r1), written in rank
 // order to out (k ints each), visited as the depth loop visits them: chunks

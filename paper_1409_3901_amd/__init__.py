@@ -25,6 +25,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported request", 3: "out of d
           7: "call too large for the static workspace"}
 PRECISION = {"plain": 0, "fp64": 0, "filtered": 1, "fp32": 1, "exact": 2}
 SWEEP = {"auto": 0, "bucket": 0, "bitonic": 1}
+METHOD = {"rcom": 0, "adia": 1}
 DEV_BITS = {1: "nonfinite", 2: "no_valid_subset", 4: "defer_overflow", 8: "exact_range",
             16: "degeneracy_limit"}
 MAX_P = 8
@@ -43,6 +44,7 @@ class Options(ctypes.Structure):
         ("deferred_capacity", ctypes.c_int64),
         ("sweep", ctypes.c_int32),
         ("prune", ctypes.c_int32),
+        ("method", ctypes.c_int32),
     ]
 
 
@@ -63,6 +65,8 @@ class Stats(ctypes.Structure):
         ("walked_sweeps", ctypes.c_uint64),
         ("pruned_subsets", ctypes.c_uint64),
         ("exact_subsets", ctypes.c_uint64),
+        ("adia_evaluations", ctypes.c_uint64),
+        ("adia_candidates", ctypes.c_uint64),
     ]
 
 
@@ -127,7 +131,8 @@ def load():
 
 
 def options(precision="filtered", autotune=True, chunk=0, grid_blocks=0, filter_scale=1.0,
-            force_exact=False, timing=False, deferred_capacity=0, sweep="auto", prune=True) -> Options:
+            force_exact=False, timing=False, deferred_capacity=0, sweep="auto", prune=True,
+            method="rcom") -> Options:
     lib = load()
     o = Options()
     lib.td_default_options(ctypes.byref(o))
@@ -141,6 +146,7 @@ def options(precision="filtered", autotune=True, chunk=0, grid_blocks=0, filter_
     o.deferred_capacity = int(deferred_capacity)
     o.sweep = SWEEP[sweep] if isinstance(sweep, str) else int(sweep)
     o.prune = 1 if prune else 0
+    o.method = METHOD[method] if isinstance(method, str) else int(method)
     return o
 
 

@@ -45,6 +45,11 @@ struct QueryDesc {
     uint64_t item_begin;// first global work item of this query
     uint32_t items;     // work items of this query
     int32_t cls;        // (p, K) class index for the batched dispatcher
+    const int32_t* kmap;// if set, only the (p-2)-subsets of these kcount points
+    int32_t kcount;     // (indices into the query's compacted points) are
+                        // swept: the candidate points of Algorithm 3, Step 5
+    int32_t zero_term;  // 1: the query's minimum is already known to be 0
+                        // (Algorithm 3, Step 2(b))
 };
 
 // Deferred (uncertain) subset.

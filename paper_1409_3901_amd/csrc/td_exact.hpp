@@ -314,7 +314,11 @@ __global__ __launch_bounds__(64) void exact_kernel(Pools pl) {
         const uint64_t* xi = pl.xi + d.v_off * 2;
         int mem[KS > 0 ? KS : 1];
         mem[0] = 0;
-        unrank_colex<KS>(pl.binom, dfr.rank, nnz, mem);
+        unrank_colex<KS>(pl.binom, dfr.rank, d.kmap ? d.kcount : nnz, mem);
+        if (d.kmap) {
+#pragma unroll
+            for (int c = 0; c < KS; ++c) mem[c] = d.kmap[mem[c]];
+        }
 #pragma unroll
         for (int c = 0; c < KS; ++c) mem[c] = uni(mem[c]);
         double A[P][KS > 0 ? KS : 1];

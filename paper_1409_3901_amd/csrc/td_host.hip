@@ -13,12 +13,14 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/td.h"
+#include "td_adia.hpp"
 #include "td_common.hpp"
 #include "td_rank.hpp"
 
@@ -33,6 +35,11 @@ extern "C" int td_resident_blocks_filt(int P, int K);
 extern "C" int td_resident_blocks_bucket(int P, int K);
 extern "C" hipError_t td_launch_exact(int P, int K, int blocks, hipStream_t s, const td::Pools* pl, int all_items);
 extern "C" uint64_t td_exact_scratch_bytes(int P);
+extern "C" hipError_t td_launch_adia_seed(const td::Pools* pl, int nq, td::AdiaSeed* seeds, hipStream_t s);
+extern "C" hipError_t td_launch_adia_eval(int P, int K, const td::Pools* pl, const td::AdiaJob* jobs, int njobs,
+                                          td::AdiaRes* res, hipStream_t s);
+extern "C" hipError_t td_launch_adia_cand(const td::Pools* pl, int nq, const td::AdiaNode* nodes, int nnodes,
+                                          uint32_t* kmask, int32_t* kmap, int32_t* kcount, hipStream_t s);
 
 // Workspace of the allocation-free entry point td_depth_noalloc: counters,
 // call parameters, the binomial table, the per-query arrays, the deferred
@@ -108,6 +115,21 @@ struct Workspace {
     hipEvent_t staged = nullptr; // the last upload has completed
     hipEvent_t ev[6] = {};
     uint64_t generation = 0;     // bumped whenever a device buffer moves
+    // buffers of Algorithm 3 (td_options.method = TD_METHOD_ADIA)
+    td::AdiaSeed* a_seeds = nullptr;
+    size_t a_seeds_cap = 0;
+    td::AdiaJob* a_jobs = nullptr;
+    size_t a_jobs_cap = 0;
+    td::AdiaRes* a_res = nullptr;
+    size_t a_res_cap = 0;
+    td::AdiaNode* a_nodes = nullptr;
+    size_t a_nodes_cap = 0;
+    uint32_t* a_kmask = nullptr;
+    size_t a_kmask_cap = 0;
+    int32_t* a_kmap = nullptr;
+    size_t a_kmap_cap = 0;
+    int32_t* a_kcount = nullptr;
+    size_t a_kcount_cap = 0;
     // captured graph of the last batched call
     std::string graph_key;
     hipGraphExec_t graph_exec = nullptr;
@@ -122,6 +144,8 @@ struct DeviceCtx {
 };
 
 struct LastCall {
+    uint64_t adia_evaluations = 0;  // Algorithm 3: subsets evaluated in Steps 2-4
+    uint64_t adia_candidates = 0;   // and candidate points of Step 5 (summed)
     Workspace* ws = nullptr;        // null after an allocation-free call
     int device = -1;
     const Counters* ctr = nullptr;  // device counters and query states of the call
@@ -216,6 +240,13 @@ void free_workspace(Workspace* w) {
     hipFree(w->deferred);
     hipFree(w->ctr);
     hipFree(w->wscratch);
+    hipFree(w->a_seeds);
+    hipFree(w->a_jobs);
+    hipFree(w->a_res);
+    hipFree(w->a_nodes);
+    hipFree(w->a_kmask);
+    hipFree(w->a_kmap);
+    hipFree(w->a_kcount);
     if (w->staging) hipHostFree(w->staging);
     if (w->staged) hipEventDestroy(w->staged);
     for (auto& e : w->ev)
@@ -241,6 +272,7 @@ td_status check_options(const td_options& o) {
     if (o.deferred_capacity < 0) return TD_ERR_INVALID_ARG;
     if (o.sweep < 0 || o.sweep > 1) return TD_ERR_INVALID_ARG;
     if (o.prune < 0 || o.prune > 1) return TD_ERR_INVALID_ARG;
+    if (o.method < 0 || o.method > 1) return TD_ERR_INVALID_ARG;
     return TD_OK;
 }
 
@@ -311,7 +343,22 @@ struct Plan {
 // kernel_k's values (1, 2, 4, 8, 16, and 10, 12, 14 at p <= 6).
 static_assert(td::kMaxClasses >= (TD_MAX_P - 1) * 5 + 5 * 3, "every (p, Kk) class of one call");
 
-td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_options& o, Plan* plan) {
+// Per-query restriction of the subsets swept (Algorithm 3, Step 5): only the
+// (p-2)-subsets of the kcount points listed at kmap (device memory), and
+// zero_term when the query's minimum is known to be 0.
+struct QueryPatch {
+    const int32_t* kmap = nullptr;
+    int32_t kcount = 0;
+    int32_t zero_term = 0;
+};
+
+// Subsets a query sweeps: C(n, p-2), or C(kcount, p-2) when restricted.
+uint64_t query_subsets(const QueryDesc& d) {
+    return binom_host(d.kmap ? d.kcount : d.n, d.p - 2);
+}
+
+td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_options& o, Plan* plan,
+                    const std::vector<QueryPatch>* patch = nullptr) {
     const int tier = subset_tier(o);
     std::map<std::pair<int, int>, int> slot;
     std::vector<int> qcls;
@@ -362,6 +409,12 @@ td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_optio
             d.M = M;
             d.idx_bits = ib;
             d.cls = c;
+            if (patch) {
+                const QueryPatch& qp = (*patch)[plan->qd.size()];
+                d.kmap = qp.kmap;
+                d.kcount = qp.kcount;
+                d.zero_term = qp.zero_term;
+            }
             plan->qd.push_back(d);
             qcls.push_back(c);
         }
@@ -378,7 +431,7 @@ td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_optio
         while (cp.chunk > 64) {
             uint64_t it = 0;
             for (const QueryDesc& d : plan->qd)
-                if (d.cls == (int)c) it += (binom_host(d.n, d.p - 2) + cp.chunk - 1) / cp.chunk;
+                if (d.cls == (int)c) it += (query_subsets(d) + cp.chunk - 1) / cp.chunk;
             if (it >= want) break;
             cp.chunk /= 2;
         }
@@ -405,7 +458,7 @@ td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_optio
         d.item_begin = item;
         d.items = 0;
         if (d.cls >= 0) {
-            const uint64_t nsub = binom_host(d.n, d.p - 2);
+            const uint64_t nsub = query_subsets(d);
             const uint64_t chunk = (uint64_t)plan->cls[d.cls].chunk;
             const uint64_t it = (nsub + chunk - 1) / chunk;
             if (it > 0xffffffffull) return TD_ERR_UNSUPPORTED;
@@ -486,21 +539,12 @@ std::string graph_signature(const Plan& plan, const Pools& pl, const td_options&
     return k;
 }
 
-td_status run(const Problem* probs, int num, const td_options& o, hipStream_t stream, bool use_graph) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return TD_ERR_NO_DEVICE;
-    DeviceCtx* dc = nullptr;
-    td_status st = ensure_device(dev, &dc);
-    if (st != TD_OK) return st;
-    Workspace* w = nullptr;
-    st = get_workspace(dc, dev, stream, &w);
-    if (st != TD_OK) return st;
-    Plan plan;
-    st = make_plan(dc, probs, num, o, &plan);
-    if (st != TD_OK) return st;
+// Device buffers, the upload of the call's descriptors and the kernels'
+// argument block for a planned call (nq > 0).
+td_status setup_call(DeviceCtx* dc, Workspace* w, const Plan& plan, const td_options& o, hipStream_t stream,
+                     Pools* out) {
+    td_status st;
     const int nq = (int)plan.qd.size();
-    if (nq == 0) return TD_OK;
-
     // device memory
     if ((st = ensure_values(w, std::max<size_t>(plan.values, 1))) != TD_OK) return st;
     if ((st = grow(w, &w->nrm, &w->pts_cap, std::max<size_t>(plan.points, 1))) != TD_OK) return st;
@@ -574,7 +618,30 @@ td_status run(const Problem* probs, int num, const td_options& o, hipStream_t st
     pl.sweep_mode = o.sweep;
     pl.prune = (o.prune && subset_tier(o) != 0) ? 1 : 0;
     pl.wscratch = w->wscratch;
+    *out = pl;
+    return TD_OK;
+}
 
+td_status run(const Problem* probs, int num, const td_options& o, hipStream_t stream, bool use_graph,
+              const std::vector<QueryPatch>* patch = nullptr) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return TD_ERR_NO_DEVICE;
+    DeviceCtx* dc = nullptr;
+    td_status st = ensure_device(dev, &dc);
+    if (st != TD_OK) return st;
+    Workspace* w = nullptr;
+    st = get_workspace(dc, dev, stream, &w);
+    if (st != TD_OK) return st;
+    Plan plan;
+    st = make_plan(dc, probs, num, o, &plan, patch);
+    if (st != TD_OK) return st;
+    const int nq = (int)plan.qd.size();
+    if (nq == 0) return TD_OK;
+    Pools pl;
+    if ((st = setup_call(dc, w, plan, o, stream, &pl)) != TD_OK) return st;
+
+    g_last.adia_evaluations = 0;
+    g_last.adia_candidates = 0;
     g_last.ws = w;
     g_last.device = w->device;
     g_last.ctr = w->ctr;
@@ -619,6 +686,240 @@ td_status run(const Problem* probs, int num, const td_options& o, hipStream_t st
     HIPCHK(hipGraphLaunch(w->graph_exec, stream));
     if (o.timing) HIPCHK(hipEventRecord(w->ev[4], stream));
     return TD_OK;
+}
+
+// ------------------------------------------- Algorithm 3 (ADIA), host side
+// The queue of critical (p-1)-sets (Steps 3-4) is kept here; every subset is
+// evaluated on the device (adia_eval_kernel), and Step 5 runs the certified
+// subset kernels restricted to the candidate points.  Up to kAdiaBatch nodes
+// of each query are popped per launch; their results are applied in queue
+// order with the deletions of Step 4(b) in between, and a popped node that an
+// earlier one deleted is passed over, so the iteration is the sequential
+// one.  Readings (as in the oracle): a node's (p-2)-subsets are taken by the
+// element left out, first element first; new nodes are appended in ascending
+// order of the added point; the seed point of Step 2(c) is the smallest
+// index next to a minimising state; Step 5's candidates also hold the points
+// of the subset that attained d0 in Step 4.
+constexpr size_t kAdiaBatch = 64;
+
+td_status adia_eval(Workspace* w, const Pools& pl, int P, int K, const std::vector<td::AdiaJob>& jobs,
+                    std::vector<td::AdiaRes>& res, hipStream_t s) {
+    res.resize(jobs.size());
+    if (jobs.empty()) return TD_OK;
+    td_status st;
+    if ((st = grow(w, &w->a_jobs, &w->a_jobs_cap, jobs.size())) != TD_OK) return st;
+    if ((st = grow(w, &w->a_res, &w->a_res_cap, jobs.size())) != TD_OK) return st;
+    HIPCHK(hipMemcpyAsync(w->a_jobs, jobs.data(), jobs.size() * sizeof(td::AdiaJob), hipMemcpyHostToDevice, s));
+    HIPCHK(td_launch_adia_eval(P, K, &pl, w->a_jobs, (int)jobs.size(), w->a_res, s));
+    HIPCHK(hipMemcpyAsync(res.data(), w->a_res, jobs.size() * sizeof(td::AdiaRes), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return TD_OK;
+}
+
+// Points reported next to a minimising state, ascending.
+std::vector<int> adia_points(const td::AdiaRes& r) {
+    std::vector<int> t(r.t, r.t + std::min(r.tcount, td::kAdiaTMax));
+    std::sort(t.begin(), t.end());
+    return t;
+}
+
+td_status run_adia(const Problem& pr, const td_options& o, hipStream_t stream) {
+    // the paper uses Algorithm 1 for n <= 2p; p < 3 has no descent
+    if (pr.p < 3 || pr.n <= 2 * pr.p) return run(&pr, 1, o, stream, false);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return TD_ERR_NO_DEVICE;
+    DeviceCtx* dc = nullptr;
+    td_status st = ensure_device(dev, &dc);
+    if (st != TD_OK) return st;
+    Workspace* w = nullptr;
+    if ((st = get_workspace(dc, dev, stream, &w)) != TD_OK) return st;
+    // ADIA's value is its own: no bound from the directions +-x_j
+    td_options po = o;
+    po.prune = 0;
+    Plan plan;
+    if ((st = make_plan(dc, &pr, 1, po, &plan)) != TD_OK) return st;
+    const int nq = (int)plan.qd.size();
+    if (nq == 0 || plan.cls.empty()) return TD_OK;
+    Pools pl;
+    if ((st = setup_call(dc, w, plan, po, stream, &pl)) != TD_OK) return st;
+    const int P = pr.p, ks = P - 2, K = plan.cls[0].K;
+    // Step 2
+    HIPCHK(td_launch_init(&pl, stream));
+    HIPCHK(td_launch_prep(&pl, plan.prep_blocks, stream));
+    if ((st = grow(w, &w->a_seeds, &w->a_seeds_cap, (size_t)nq)) != TD_OK) return st;
+    HIPCHK(td_launch_adia_seed(&pl, nq, w->a_seeds, stream));
+    std::vector<td::AdiaSeed> seeds((size_t)nq);
+    HIPCHK(hipMemcpyAsync(seeds.data(), w->a_seeds, (size_t)nq * sizeof(td::AdiaSeed), hipMemcpyDeviceToHost,
+                          stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    enum { kAdia = 0, kZero = 1, kRcom = 2 };
+    struct QueryRun {
+        int mode = kRcom;
+        std::map<std::vector<int>, int> Q;
+        std::deque<std::vector<int>> N;
+        int d0 = 0;
+        std::vector<int> bestJ;
+        uint64_t evals = 0;
+    };
+    std::vector<QueryRun> R((size_t)nq);
+    uint64_t evaluations = 0;
+    // Step 2(c): the seed subsets
+    std::vector<td::AdiaJob> jobs;
+    std::vector<int> jq;
+    for (int q = 0; q < nq; ++q) {
+        if (seeds[q].kneg == 0) { R[q].mode = kZero; continue; }
+        if (!seeds[q].ok) continue;
+        td::AdiaJob j;
+        std::memset(&j, 0, sizeof(j));
+        j.q = q;
+        std::vector<int> I(seeds[q].idx, seeds[q].idx + ks);
+        std::sort(I.begin(), I.end());
+        for (int c = 0; c < ks; ++c) j.idx[c] = I[c];
+        jobs.push_back(j);
+        jq.push_back(q);
+    }
+    std::vector<td::AdiaRes> res;
+    if ((st = adia_eval(w, pl, P, K, jobs, res, stream)) != TD_OK) return st;
+    evaluations += jobs.size();
+    for (size_t e = 0; e < jobs.size(); ++e) {
+        QueryRun& qr = R[(size_t)jq[e]];
+        std::vector<int> I(jobs[e].idx, jobs[e].idx + ks);
+        if (res[e].term < 0) continue;
+        int h = -1;
+        for (int v : adia_points(res[e]))
+            if (std::find(I.begin(), I.end(), v) == I.end()) { h = v; break; }
+        if (h < 0) continue;
+        std::vector<int> C0 = I;
+        C0.push_back(h);
+        std::sort(C0.begin(), C0.end());
+        qr.mode = kAdia;
+        qr.Q[C0] = res[e].term;
+        qr.N.push_back(C0);
+        qr.d0 = res[e].term;
+        qr.bestJ = I;
+    }
+    // Steps 3-4
+    while (true) {
+        jobs.clear();
+        std::vector<std::vector<std::vector<int>>> popped((size_t)nq);
+        for (int q = 0; q < nq; ++q) {
+            QueryRun& qr = R[(size_t)q];
+            if (qr.mode != kAdia) continue;
+            // a descent longer than the full enumeration gains nothing: that
+            // query falls back to Algorithm 1
+            if (qr.evals > 4 * binom_host(pr.n, ks) + 4096) {
+                qr.mode = kRcom;
+                continue;
+            }
+            while (!qr.N.empty() && popped[(size_t)q].size() < kAdiaBatch) {
+                const std::vector<int> F = qr.N.front();
+                qr.N.pop_front();
+                for (int r = 0; r < ks + 1; ++r) {
+                    td::AdiaJob j;
+                    std::memset(&j, 0, sizeof(j));
+                    j.q = q;
+                    int c2 = 0;
+                    for (int c = 0; c < ks + 1; ++c)
+                        if (c != r) j.idx[c2++] = F[(size_t)c];
+                    jobs.push_back(j);
+                }
+                qr.evals += (uint64_t)ks + 1;
+                popped[(size_t)q].push_back(F);
+            }
+        }
+        if (jobs.empty()) break;
+        if ((st = adia_eval(w, pl, P, K, jobs, res, stream)) != TD_OK) return st;
+        evaluations += jobs.size();
+        size_t e0 = 0;
+        for (int q = 0; q < nq; ++q) {
+            QueryRun& qr = R[(size_t)q];
+            if (qr.mode != kAdia) {
+                e0 += popped[(size_t)q].size() * ((size_t)ks + 1);
+                continue;
+            }
+            for (const std::vector<int>& F : popped[(size_t)q]) {
+                const size_t base = e0;
+                e0 += (size_t)ks + 1;
+                if (!qr.Q.count(F)) continue;   // deleted by an earlier node: not popped
+                for (int r = 0; r < ks + 1; ++r) {
+                    const td::AdiaRes& rr = res[base + (size_t)r];
+                    if (rr.term < 0) continue;
+                    std::vector<int> J(jobs[base + (size_t)r].idx, jobs[base + (size_t)r].idx + ks);
+                    for (int v : adia_points(rr)) {
+                        if (std::find(F.begin(), F.end(), v) != F.end()) continue;
+                        std::vector<int> Nn = J;
+                        Nn.push_back(v);
+                        std::sort(Nn.begin(), Nn.end());
+                        if (!qr.Q.count(Nn)) {
+                            qr.Q[Nn] = rr.term;
+                            qr.N.push_back(Nn);
+                        }
+                    }
+                    if (qr.d0 > rr.term) {
+                        qr.d0 = rr.term;
+                        qr.bestJ = J;
+                        break;
+                    }
+                }
+                for (auto it = qr.Q.begin(); it != qr.Q.end();) {
+                    if (it->second > qr.d0) it = qr.Q.erase(it); else ++it;
+                }
+                std::deque<std::vector<int>> keep;
+                for (auto& f : qr.N)
+                    if (qr.Q.count(f)) keep.push_back(f);
+                qr.N.swap(keep);
+            }
+        }
+    }
+    // Step 5(a): candidate points
+    std::vector<td::AdiaNode> nodes;
+    for (int q = 0; q < nq; ++q) {
+        const QueryRun& qr = R[(size_t)q];
+        if (qr.mode != kAdia) continue;
+        for (const auto& e : qr.Q) {
+            td::AdiaNode nd;
+            std::memset(&nd, 0, sizeof(nd));
+            nd.q = q;
+            nd.count = ks + 1;
+            for (int c = 0; c <= ks; ++c) nd.idx[c] = e.first[(size_t)c];
+            nodes.push_back(nd);
+        }
+        td::AdiaNode nd;
+        std::memset(&nd, 0, sizeof(nd));
+        nd.q = q;
+        nd.count = ks;
+        for (int c = 0; c < ks; ++c) nd.idx[c] = qr.bestJ[(size_t)c];
+        nodes.push_back(nd);
+    }
+    if ((st = grow(w, &w->a_nodes, &w->a_nodes_cap, std::max<size_t>(nodes.size(), 1))) != TD_OK) return st;
+    if ((st = grow(w, &w->a_kmask, &w->a_kmask_cap, (size_t)nq * (td::kMaxN / 32))) != TD_OK) return st;
+    if ((st = grow(w, &w->a_kmap, &w->a_kmap_cap, (size_t)nq * td::kMaxN)) != TD_OK) return st;
+    if ((st = grow(w, &w->a_kcount, &w->a_kcount_cap, (size_t)nq)) != TD_OK) return st;
+    if (!nodes.empty())
+        HIPCHK(hipMemcpyAsync(w->a_nodes, nodes.data(), nodes.size() * sizeof(td::AdiaNode), hipMemcpyHostToDevice,
+                              stream));
+    HIPCHK(td_launch_adia_cand(&pl, nq, w->a_nodes, (int)nodes.size(), w->a_kmask, w->a_kmap, w->a_kcount, stream));
+    std::vector<int32_t> kcount((size_t)nq);
+    HIPCHK(hipMemcpyAsync(kcount.data(), w->a_kcount, (size_t)nq * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    // Step 5(b): the certified sweeps over the candidates' subsets
+    std::vector<QueryPatch> patch((size_t)nq);
+    uint64_t cands = 0;
+    for (int q = 0; q < nq; ++q) {
+        if (R[(size_t)q].mode == kAdia) {
+            patch[(size_t)q].kmap = w->a_kmap + (size_t)q * td::kMaxN;
+            patch[(size_t)q].kcount = kcount[(size_t)q];
+            cands += (uint64_t)kcount[(size_t)q];
+        } else if (R[(size_t)q].mode == kZero) {
+            patch[(size_t)q].kmap = w->a_kmap;   // no subset: the minimum is 0
+            patch[(size_t)q].kcount = 0;
+            patch[(size_t)q].zero_term = 1;
+        }
+    }
+    st = run(&pr, 1, po, stream, false, &patch);
+    g_last.adia_evaluations = evaluations;
+    g_last.adia_candidates = cands;
+    return st;
 }
 
 // ------------------------------------------------ allocation-free call
@@ -808,6 +1109,8 @@ td_status run_noalloc(const Problem& pr, const td_options& o, hipStream_t stream
     hipLaunchKernelGGL(noalloc_setup_kernel, dim3(std::max(sblocks, 1)), dim3(256), 0, stream, a);
     HIPCHK(hipGetLastError());
 
+    g_last.adia_evaluations = 0;
+    g_last.adia_candidates = 0;
     g_last.ws = nullptr;
     g_last.device = dev;
     g_last.ctr = pl.ctr;
@@ -854,6 +1157,7 @@ td_status td_depth_ex(const double* X, int64_t n, int32_t p, const double* Z, in
     std::lock_guard<std::mutex> lk(g_mu);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return TD_ERR_NO_DEVICE;
+    if (o.method == TD_METHOD_ADIA) return run_adia(pr, o, (hipStream_t)stream);
     return run(&pr, 1, o, (hipStream_t)stream, false);
 }
 
@@ -868,6 +1172,7 @@ td_status td_depth_batched(const td_problem* probs, int32_t num, const td_option
     td_options o = opt ? *opt : defaults();
     td_status st = check_options(o);
     if (st != TD_OK) return st;
+    if (o.method != TD_METHOD_RCOM) return TD_ERR_UNSUPPORTED;
     std::vector<Problem> pv(num);
     int64_t total = 0;
     for (int i = 0; i < num; ++i) {
@@ -889,6 +1194,7 @@ td_status td_depth_noalloc(const double* X, int64_t n, int32_t p, const double* 
     td_options o = opt ? *opt : defaults();
     td_status st = check_options(o);
     if (st != TD_OK) return st;
+    if (o.method != TD_METHOD_RCOM) return TD_ERR_UNSUPPORTED;
     Problem pr{X, n, p, Z, m, counts};
     st = check_problem(pr);
     if (st != TD_OK) return st;
@@ -919,6 +1225,8 @@ td_status td_get_stats(td_stats* out) {
     out->walked_sweeps = c.walked;
     out->pruned_subsets = c.pruned;
     out->exact_subsets = c.exact_done;
+    out->adia_evaluations = g_last.adia_evaluations;
+    out->adia_candidates = g_last.adia_candidates;
     std::vector<QueryState> qs(g_last.nq);
     if (g_last.nq > 0) HIPCHK(hipMemcpy(qs.data(), g_last.qs, qs.size() * sizeof(QueryState), hipMemcpyDeviceToHost));
     int dst = 0;

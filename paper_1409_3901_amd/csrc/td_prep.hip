@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void prep_kernel(Pools pl) {
             st.nnz = nnz;
             st.n0 = n - nnz;
             st.status = (bad ? kStNonfinite : 0) | (ints_ok ? 0 : kStNoExactInts);
-            st.min_term = 0x7fffffff;
+            st.min_term = d.zero_term ? 0 : 0x7fffffff;
             st.ub_term = ub;
             if (p == 1) st.min_term = min(pos1, neg1);
             if (nnz == 0) st.min_term = 0;

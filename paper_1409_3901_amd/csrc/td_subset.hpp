@@ -1042,7 +1042,11 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
         const QueryState st = pl.qs[q];
         if (st.status & kStNonfinite) continue;
         const int nnz = uni(st.nnz);
-        const uint64_t nsub = uni64(binom_lookup(pl.binom, nnz, KS));
+        // ground set of the enumeration: all nonzero points, or the
+        // candidate points of a restricted query
+        const int32_t* kmap = d.kmap;
+        const int ng = kmap ? uni(d.kcount) : nnz;
+        const uint64_t nsub = uni64(binom_lookup(pl.binom, ng, KS));
         const uint64_t r0 = uni64((item - d.item_begin) * (uint64_t)chunk);
         const uint64_t r1 = uni64(min(r0 + (uint64_t)chunk, nsub));
         if (r0 >= r1) continue;
@@ -1070,7 +1074,11 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
             if (myr < r1) {
                 int cc[KS > 0 ? KS : 1];
                 cc[0] = 0;
-                unrank_colex<KS>(pl.binom, myr, nnz, cc);
+                unrank_colex<KS>(pl.binom, myr, ng, cc);
+                if (kmap) {
+#pragma unroll
+                    for (int c = 0; c < KS; ++c) cc[c] = kmap[cc[c]];
+                }
                 double A[P][KS > 0 ? KS : 1];
 #pragma unroll
                 for (int col = 0; col < KS; ++col)

@@ -1,0 +1,104 @@
+"""The paper's adaptive algorithm (Algorithm 3, td_options.method = ADIA) on
+the GPU: the descent of Steps 2-4 and Step 5's certified sweeps over the
+subsets of the candidate points.  In general position its counts must equal
+the exact counts (and the oracle's ADIA); on any data they must never lie
+below the exact count."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from conftest import to_dev
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def run(td, dev, X, Z, **kw):
+    c = td.depth(to_dev(X, dev), to_dev(np.atleast_2d(Z), dev), method="adia", **kw)
+    return c.cpu().numpy().astype(np.int64), td.get_stats()
+
+
+def test_adia_c1(td, dev):
+    X, Z = workloads.c1()
+    g = json.load(open(os.path.join(GOLD, "c1.json")))["counts"]
+    exp = np.array([g[str(q)] for q in range(Z.shape[0])])
+    got, st = run(td, dev, X, Z)
+    assert st["device_status"] == 0
+    assert st["adia_evaluations"] > 0
+    assert np.array_equal(got, exp), (got, exp)
+    a, _ = oracle.depth_adia(X, Z)
+    assert np.array_equal(got, a)
+
+
+@pytest.mark.parametrize("p,n", [(3, 200), (4, 90), (5, 50), (6, 28), (7, 20), (8, 19)])
+@pytest.mark.parametrize("sweep", ["auto", "bitonic"])
+def test_adia_general_position_vs_oracle(td, dev, p, n, sweep):
+    rng = np.random.default_rng(500 + 11 * p + n)
+    X = rng.standard_normal((n, p))
+    Z = np.vstack([0.3 * rng.standard_normal((3, p)), X[:2], 1.5 * rng.standard_normal((2, p)),
+                   workloads.outside_hull_query(X, rng)])
+    got, st = run(td, dev, X, Z, sweep=sweep)
+    assert st["device_status"] == 0
+    exp = oracle.depth_counts(X, Z)
+    assert np.array_equal(got, exp), (got, exp)
+    a, _ = oracle.depth_adia(X, Z)
+    assert np.array_equal(got, a)
+
+
+def test_adia_c3_sample_queries(td, dev):
+    """The benchmark workload (p = 5, n = 500): four queries against the
+    stored exact counts."""
+    X, Z = workloads.c3()
+    g = json.load(open(os.path.join(GOLD, "c3.json")))["counts"]
+    qs = [0, 5, 16, 20]
+    exp = np.array([g[str(q)] for q in qs])
+    got, st = run(td, dev, X, Z[qs])
+    assert st["device_status"] == 0
+    assert np.array_equal(got, exp), (got, exp)
+    assert st["adia_candidates"] < 4 * X.shape[0]
+
+
+def test_adia_never_below_depth_on_degenerate_data(td, dev):
+    rng = np.random.default_rng(94)
+    bad = []
+    for t in range(30):
+        p = int(rng.integers(3, 6))
+        kind = t % 3
+        if kind == 0:
+            X, Z = workloads.lattice_small(rng, p, int(rng.integers(p + 6, 16)), R=2)
+        elif kind == 1:
+            X, Z = workloads.ray_duplicated(rng, p, int(rng.integers(5, 9)))
+        else:
+            X, Z = workloads.near_degenerate(rng, p, int(rng.integers(p + 6, 16)))
+        got, st = run(td, dev, X, Z)
+        exp = oracle.depth_counts(X, Z)
+        if st["device_status"] == 0 and got[0] < exp[0]:
+            bad.append((t, int(got[0]), int(exp[0])))
+    assert not bad, bad
+
+
+def test_adia_small_samples_and_p2_use_algorithm_1(td, dev):
+    rng = np.random.default_rng(95)
+    for p, n in [(2, 40), (3, 6), (5, 10)]:
+        X = rng.standard_normal((n, p))
+        Z = rng.standard_normal((3, p))
+        got, st = run(td, dev, X, Z)
+        assert np.array_equal(got, oracle.depth_counts(X, Z))
+        assert st["adia_evaluations"] == 0
+
+
+def test_adia_unsupported_entry_points(td, dev):
+    import torch
+    X = to_dev(np.random.default_rng(1).standard_normal((20, 3)), dev)
+    Z = to_dev(np.zeros((1, 3)), dev)
+    with pytest.raises(td.TDError) as e:
+        td.depth_batched([(X, Z)], method="adia")
+    assert e.value.code == 2
+    out = torch.zeros(1, dtype=torch.int32, device=dev)
+    with pytest.raises(td.TDError) as e:
+        td.depth_noalloc(X, Z, out, method="adia")
+    assert e.value.code == 2

@@ -174,3 +174,51 @@ def test_literal_variants_fail():
         X, Z = workloads.ray_duplicated(rng, 3, 4)
         diffs += int(literal.depth_literal(X, Z[0]) != oracle.depth_counts(X, Z)[0])
     assert diffs > 0
+
+
+# ---------------------------------------------------------- Algorithm 3 (ADIA)
+def test_adia_oracle_equals_depth_in_general_position():
+    """The paper reports the exact depth from its adaptive algorithm in all
+    its experiments (general position); the oracle's ADIA must agree with the
+    exact count on such data, across dimensions and depths (shallow, deep,
+    sample points, outside the hull)."""
+    rng = np.random.default_rng(91)
+    for p, n in [(3, 120), (4, 60), (5, 36), (6, 22)]:
+        X = rng.standard_normal((n, p))
+        Z = np.vstack([0.3 * rng.standard_normal((3, p)), X[:2], 1.5 * rng.standard_normal((2, p)),
+                       workloads.outside_hull_query(X, rng)])
+        got, ks = oracle.depth_adia(X, Z)
+        exp = oracle.depth_counts(X, Z)
+        assert np.array_equal(got, exp), (p, n, got, exp)
+        # Step 5 looks at fewer points than the sample for shallow queries
+        assert np.all(ks[ks >= 0] <= n)
+
+
+def test_adia_oracle_never_below_depth():
+    """ADIA's value is attained by some subset, so it is never below the
+    depth, whatever the data (degenerate families)."""
+    rng = np.random.default_rng(92)
+    for t in range(40):
+        p = int(rng.integers(3, 6))
+        kind = t % 3
+        if kind == 0:
+            X, Z = workloads.lattice_small(rng, p, int(rng.integers(p + 6, 16)), R=2)
+        elif kind == 1:
+            X, Z = workloads.ray_duplicated(rng, p, int(rng.integers(5, 9)))
+        else:
+            X, Z = workloads.near_degenerate(rng, p, int(rng.integers(p + 6, 16)))
+        got, _ = oracle.depth_adia(X, Z)
+        exp = oracle.depth_counts(X, Z)
+        assert got[0] >= exp[0], (t, got, exp)
+
+
+def test_adia_oracle_small_samples_use_algorithm_1():
+    """n <= 2p or p < 3: the paper's advice is Algorithm 1 (reported with
+    ksize -1), so the count is the exact one."""
+    rng = np.random.default_rng(93)
+    for p, n in [(2, 30), (3, 6), (5, 10)]:
+        X = rng.standard_normal((n, p))
+        Z = rng.standard_normal((2, p))
+        got, ks = oracle.depth_adia(X, Z)
+        assert np.array_equal(got, oracle.depth_counts(X, Z))
+        assert np.all(ks == -1)
