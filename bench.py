@@ -90,8 +90,9 @@ def main():
                     help="every workload against its stored oracle counts: mismatches, "
                          "fallback rates and time of the filtered and plain tiers")
     ap.add_argument("--paper-grid", action="store_true",
-                    help="the paper's simulation grid (X ~ N(0, I_p), z = 0, one query), "
-                         "timed per query beside the paper's own timings as context")
+                    help="the paper's simulation grid (X ~ N(0, I_p), z = alpha 1_p, one query), "
+                         "Algorithm 1 (RCom) and Algorithm 3 (ADIA) timed per query beside the "
+                         "paper's own timings as context")
     ap.add_argument("--p2", action="store_true",
                     help="p = 2, n = 1024, m = 1024 queries: one sweep per query (Algorithm 2 "
                          "alone), filtered and plain tiers, against stored oracle counts")
@@ -193,6 +194,9 @@ def main():
                    "p": p, "n": n, "m": m,
                    "precision": "fp64-plain" if a.precision == "plain" else "fp32-filtered+fp64+exact",
                    "sweep": "bitonic" if a.precision != "filtered" else "bucketed"},
+        "value_definition": "enumerated subsets (sum over queries of C(n'_q, p-2)) resolved per second; "
+                            "subsets the pruning bound settles without a sweep are included, see "
+                            "processed_sweeps_per_s",
         "queries_per_s": m / (ms / 1e3),
         "sweeps_per_step": sweeps,
         "fp64_rechecks_per_sweep": st["fp64_rechecks"] / max(1, st["subsets_swept"]),
@@ -235,6 +239,9 @@ def main():
                              "subset_kernel_ms": psub,
                              "mismatches_vs_filtered": int(np.sum(pcounts != counts))}
         res["speedup_filtered_vs_plain"] = pms / ms
+        # the same full bitonic sort in both: the factor due to the arithmetic
+        # alone (float32 filter with certification against plain float64)
+        res["speedup_precision_only"] = pms / bms
     if not a.no_cpu:
         res["cpu_baseline"] = cpu_baseline(X, Z, a.cpu_seconds)
     print(json.dumps(res), flush=True)
@@ -443,30 +450,68 @@ PAPER_TABLE2_S = {
 }
 
 
+# The paper's timings of its adaptive algorithm (Table 3: ADIA, seconds per
+# query, the same design at z = alpha 1_p), quoted as context only.
+PAPER_TABLE3_S = {
+    (3, 0.0): [0.0193, 0.0634, 0.0503, 0.1297, 0.4372], (3, 0.4): [0.0167, 0.0470, 0.0668, 0.0968, 0.3418],
+    (3, 0.8): [0.0065, 0.0131, 0.0180, 0.0460, 0.3248], (3, 1.2): [0.0067, 0.0136, 0.0186, 0.0390, 0.1220],
+    (4, 0.0): [0.3416, 0.3211, 1.7991, 6.5374, 60.6911], (4, 0.4): [0.0607, 0.1704, 0.5131, 1.7255, 11.9404],
+    (4, 0.8): [0.1070, 0.1172, 0.1140, 0.5171, 1.7526], (4, 1.2): [0.1373, 0.1465, 0.0538, 0.2278, 0.9409],
+    (5, 0.0): [0.9466, 6.9212, 68.0360, 404.5147, 13177.5227], (5, 0.4): [0.4048, 1.0052, 8.3791, 43.6717, 609.6461],
+    (5, 0.8): [1.2751, 1.1352, 1.6600, 5.3665, 15.8776], (5, 1.2): [0.1923, 0.1001, 0.3339, 0.3162, 1.5744],
+    (6, 0.0): [12.3953, 95.3378, 3883.9385, None, None], (6, 0.4): [4.3607, 18.3686, 173.8880, 1504.1087, None],
+    (6, 0.8): [0.1638, 0.2295, 62.8009, 158.7744, 1777.3669], (6, 1.2): [1.1149, 3.0121, 1.4400, 4.9680, 19.3288],
+}
+GRID_N = [40, 80, 160, 320, 640]
+
+
 def bench_paper_grid(td, workloads, torch, np, dev):
-    """One query z = 0 on X ~ N(0, I_p) for the (p, n) points of the paper's
-    simulation table that fit the library (n <= 1024): the GPU time per query
-    (the library's own HIP events over the whole call, best of 5) beside the
-    paper's seconds per query."""
+    """The paper's simulation design (X ~ N(0, I_p), seeded; one query
+    z = alpha 1_p) for p = 3..6, n = 40..640 and alpha in {0, 0.4, 0.8, 1.2}:
+    the time of one td_depth call by Algorithm 1 (RCom) and by Algorithm 3
+    (ADIA), best of 3 (host clock around the call and a synchronisation; the
+    ADIA call synchronises between its steps), the two counts (which must
+    agree: the rows report it), ADIA's evaluated subsets and candidate points,
+    and the paper's seconds for RCom (Table 2, alpha = 0) and ADIA (Table 3)
+    as context.  p = 6 stops at n = 320 (n = 640 sweeps 6.9e9 subsets per
+    method and alpha)."""
     rows = []
-    for (p, n), paper_s in sorted(PAPER_TABLE2_S.items()):
-        X, Z = workloads.grid(p, n, 0.0)
-        Xd = torch.from_numpy(X).to(dev)
-        Zd = torch.from_numpy(Z).to(dev)
-        td.depth(Xd, Zd)
-        best = None
-        for _ in range(5):
-            c = td.depth(Xd, Zd, timing=True)
-            torch.cuda.synchronize()
-            ms = td.get_stats()["total_ms"]
-            best = ms if best is None else min(best, ms)
-        rows.append({"p": p, "n": n, "depth": int(c.cpu()[0]), "gpu_ms_per_query": best,
-                     "subsets": math.comb(n, p - 2), "paper_s_per_query": paper_s,
-                     "paper_over_gpu": paper_s * 1e3 / best})
-        print("[grid] p=%d n=%d %.3f ms" % (p, n, best), file=sys.stderr, flush=True)
-    print(json.dumps({"metric": "seconds per query on the paper's simulation grid (context)",
+    for p in (3, 4, 5, 6):
+        for ni, n in enumerate(GRID_N):
+            if p == 6 and n > 320:
+                continue
+            for alpha in (0.0, 0.4, 0.8, 1.2):
+                X, Z = workloads.grid(p, n, alpha)
+                Xd = torch.from_numpy(X).to(dev)
+                Zd = torch.from_numpy(Z).to(dev)
+                row = {"p": p, "n": n, "alpha": alpha, "subsets": math.comb(n, p - 2)}
+                for meth in ("rcom", "adia"):
+                    td.depth(Xd, Zd, method=meth)
+                    torch.cuda.synchronize()
+                    best = None
+                    for _ in range(3):
+                        t = time.perf_counter()
+                        c = td.depth(Xd, Zd, method=meth)
+                        torch.cuda.synchronize()
+                        dt = (time.perf_counter() - t) * 1e3
+                        best = dt if best is None else min(best, dt)
+                    st = td.get_stats()
+                    row[meth + "_ms"] = best
+                    row[meth + "_count"] = int(c.cpu()[0])
+                    if meth == "adia":
+                        row["adia_evaluations"] = st["adia_evaluations"]
+                        row["adia_candidates"] = st["adia_candidates"]
+                row["counts_agree"] = row["rcom_count"] == row["adia_count"]
+                row["paper_rcom_s"] = PAPER_TABLE2_S.get((p, n)) if alpha == 0.0 else None
+                row["paper_adia_s"] = PAPER_TABLE3_S[(p, alpha)][ni]
+                rows.append(row)
+                print("[grid] p=%d n=%d alpha=%.1f rcom %.3f ms adia %.3f ms (%d / %d)"
+                      % (p, n, alpha, row["rcom_ms"], row["adia_ms"], row["rcom_count"], row["adia_count"]),
+                      file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "ms per query on the paper's simulation grid, RCom and ADIA (context)",
                       "unit": "ms", "n_gpus": 1, "data": "synthetic",
-                      "paper_hardware": "Intel Core i7-2670QM 2.2 GHz, Matlab 7.8 (Table 2)",
+                      "paper_hardware": "Intel Core i7-2670QM 2.2 GHz, Matlab 7.8 (Tables 2 and 3)",
+                      "all_counts_agree": all(r["counts_agree"] for r in rows),
                       "rows": rows}), flush=True)
 
 

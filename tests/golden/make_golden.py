@@ -8,6 +8,7 @@ are skipped.
     python tests/golden/make_golden.py [c1 c2 c3 c5 c4 p2] [--threads T]
     python tests/golden/make_golden.py c5 --queries 15,14,13 --part b
     python tests/golden/make_golden.py c4wide wide
+    python tests/golden/make_golden.py adia
 
 c4wide stores, in ``c4.wide.json``, queries of the batched workload's p = 5
 datasets with n > 512 (the kernels holding 10, 12 or 14 points per lane),
@@ -111,7 +112,34 @@ def run_wide(threads: int):
             print("wide %s -> %d (%.1fs)" % (key, v, time.time() - t), flush=True)
 
 
+def run_adia(threads: int, exact_too):
+    """adia.json: Algorithm 3 (oracle_depth_adia) on workloads.ADIA_GRID_CASES,
+    keyed "p,n,alpha"; "exact" holds Algorithm 1's count for the cases listed
+    in `exact_too`."""
+    path = os.path.join(HERE, "adia.json")
+    obj = _load(path) or {"config": "adia", "source": "oracle/td_oracle.cpp (oracle_depth_adia, oracle_depth)",
+                          "adia": {}, "candidates": {}, "exact": {}}
+    for p, n, alpha in workloads.ADIA_GRID_CASES:
+        key = "%d,%d,%.1f" % (p, n, alpha)
+        X, Z = workloads.grid(p, n, alpha)
+        if key not in obj["adia"]:
+            t = time.time()
+            v, ks = oracle.depth_adia(X, Z, threads=threads)
+            obj["adia"][key] = int(v[0])
+            obj["candidates"][key] = int(ks[0])
+            _save(path, obj)
+            print("adia %s -> %d (%d candidates, %.1fs)" % (key, v[0], ks[0], time.time() - t), flush=True)
+        if key in exact_too and key not in obj["exact"]:
+            t = time.time()
+            v = int(oracle.depth_counts(X, Z, threads=threads)[0])
+            obj["exact"][key] = v
+            _save(path, obj)
+            print("exact %s -> %d (%.1fs)" % (key, v, time.time() - t), flush=True)
+
+
 def run(cfg: str, threads: int, queries=None, part=None):
+    if cfg == "adia":
+        return run_adia(threads, {"6,320,0.0", "5,640,0.0"})
     if cfg == "c4wide":
         return run_c4wide(threads)
     if cfg == "wide":

@@ -53,7 +53,7 @@ __all__ = [
     "c1", "c2", "c3", "c4", "c5", "p2", "grid", "observations", "config",
     "lattice_small", "ray_duplicated", "rank_deficient", "near_degenerate",
     "symmetric", "duplicated", "outside_hull_query", "unimodular", "wide",
-    "WIDE_CASES",
+    "WIDE_CASES", "ADIA_GRID_CASES",
 ]
 
 
@@ -267,6 +267,12 @@ def wide(name: str):
     X = rng.standard_normal((n, p))
     Z = np.vstack([0.3 * rng.standard_normal((1, p)), X[n // 3:n // 3 + 1]])
     return _f64(X), _f64(Z)
+
+
+# Grid cases (p, n, alpha) whose Algorithm 3 counts are stored: the deep
+# query at p = 6, n = 320 is one where the paper's adaptive algorithm stops
+# above the depth.
+ADIA_GRID_CASES = [(6, 320, 0.0), (6, 320, 0.4), (5, 640, 0.0), (5, 640, 0.4), (4, 640, 0.8)]
 
 
 def config(name: str):
