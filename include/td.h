@@ -158,6 +158,10 @@ typedef struct {
                                     descent (Algorithm 3, Steps 2-4) */
     uint64_t adia_candidates;    /* TD_METHOD_ADIA: candidate points of Step 5,
                                     summed over the queries */
+    uint64_t f64_items;          /* work items of the bucketed sweep (p >= 3)
+                                    finished by its float64 pass: from the
+                                    first sweep of the item that needed the
+                                    float64 re-check or re-order on */
 } td_stats;
 
 /* One independent depth problem of a batch (pointers as for td_depth). */

@@ -67,6 +67,7 @@ class Stats(ctypes.Structure):
         ("exact_subsets", ctypes.c_uint64),
         ("adia_evaluations", ctypes.c_uint64),
         ("adia_candidates", ctypes.c_uint64),
+        ("f64_items", ctypes.c_uint64),
     ]
 
 

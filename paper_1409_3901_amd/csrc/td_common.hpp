@@ -82,6 +82,18 @@ struct Counters {
     unsigned long long defer_next;    // deferred-queue write position
     unsigned long long prep_next;     // query counter of the preparation kernel
     unsigned long long work_next[kMaxClasses];   // work-item counter per class
+    unsigned long long redo_count[kMaxClasses];  // work items handed to the
+                                                 // float64 pass, per class
+    unsigned long long redo_next[kMaxClasses];   // its work counter per class
+};
+
+// A work item of the bucketed subset kernel left to its float64 pass: the
+// subsets of the batch of 64 at colex rank `base` whose bits are set in
+// `mask`, and every subset of the item from base + 64 on.
+struct RedoItem {
+    uint64_t item;
+    uint64_t base;
+    uint64_t mask;
 };
 
 // Per-call parameters in device memory, so that the kernel arguments (and a
@@ -112,6 +124,8 @@ struct Pools {
     Deferred* deferred;
     Counters* ctr;
     uint64_t defer_cap;
+    RedoItem* redo;     // work items for the float64 pass (shared by the
+    uint64_t redo_cap;  // classes, which run one after the other)
     float filter_scale;
     int32_t force_exact;
     int32_t cls;        // class slot of this launch (subset and exact kernels)

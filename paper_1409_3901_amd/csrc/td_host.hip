@@ -30,6 +30,7 @@ extern "C" hipError_t td_launch_finalize(const td::Pools* pl, int blocks, hipStr
 extern "C" hipError_t td_launch_subset_plain(int P, int K, int blocks, hipStream_t s, const td::Pools* pl);
 extern "C" hipError_t td_launch_subset_filt(int P, int K, int blocks, hipStream_t s, const td::Pools* pl);
 extern "C" hipError_t td_launch_subset_bucket(int P, int K, int blocks, hipStream_t s, const td::Pools* pl);
+extern "C" hipError_t td_launch_subset_bucket64(int P, int K, int blocks, hipStream_t s, const td::Pools* pl);
 extern "C" int td_resident_blocks_plain(int P, int K);
 extern "C" int td_resident_blocks_filt(int P, int K);
 extern "C" int td_resident_blocks_bucket(int P, int K);
@@ -58,6 +59,7 @@ using td::Deferred;
 using td::Pools;
 using td::QueryDesc;
 using td::QueryState;
+using td::RedoItem;
 
 #define HIPCHK(x)                                   \
     do {                                            \
@@ -66,6 +68,7 @@ using td::QueryState;
     } while (0)
 
 constexpr int64_t kDefaultDeferCap = 1 << 25;
+constexpr uint64_t kMaxRedo = 1ull << 22;   // work items of the float64 pass per call
 
 using td::binom_host;
 
@@ -107,6 +110,8 @@ struct Workspace {
     CallParams* cp = nullptr;
     Deferred* deferred = nullptr;
     int64_t defer_cap = 0;
+    RedoItem* redo = nullptr;
+    uint64_t redo_cap = 0;
     Counters* ctr = nullptr;
     uint8_t* wscratch = nullptr;
     size_t wscratch_cap = 0;
@@ -152,6 +157,7 @@ struct LastCall {
     const QueryState* qs = nullptr;
     int nq = 0;
     int timing = 0;   // 1: per stage, 2: whole call only
+    uint64_t redo_cap = 0;  // entries of the float64 pass's work list
 };
 
 std::mutex g_mu;
@@ -238,6 +244,7 @@ void free_workspace(Workspace* w) {
     hipFree(w->qs);
     hipFree(w->cp);
     hipFree(w->deferred);
+    hipFree(w->redo);
     hipFree(w->ctr);
     hipFree(w->wscratch);
     hipFree(w->a_seeds);
@@ -507,6 +514,11 @@ td_status enqueue(const Plan& plan, const Pools& base, const td_options& o, hipS
                        : tier == 1 ? td_launch_subset_filt(cp.p, cp.K, cp.shape.blocks, s, &pl)
                                    : td_launch_subset_bucket(cp.p, cp.Kk, cp.shape.blocks, s, &pl);
         if (e != hipSuccess) return TD_ERR_HIP;
+        // the float64 pass of the bucketed sweep (p >= 3): the work items the
+        // launch above handed over, usually none
+        if (tier == td::kFiltBucket && cp.p >= 3 &&
+            td_launch_subset_bucket64(cp.p, cp.Kk, cp.shape.blocks, s, &pl) != hipSuccess)
+            return TD_ERR_HIP;
     }
     if (timing) HIPCHK(hipEventRecord(w->ev[2], s));
     if (tier != 0) {
@@ -529,7 +541,7 @@ std::string graph_signature(const Plan& plan, const Pools& pl, const td_options&
     std::string k = std::to_string(subset_tier(o)) + "|" + std::to_string(w->generation) + "|" +
                      std::to_string(plan.prep_blocks) + "|" + std::to_string(plan.fin_blocks) + "|" +
                      std::to_string(pl.force_exact) + "|" + std::to_string(pl.filter_scale) + "|" +
-                     std::to_string(pl.defer_cap) + "|" +
+                     std::to_string(pl.defer_cap) + "|" + std::to_string(pl.redo_cap) + "|" +
                      std::to_string(pl.sweep_mode) + "|" + std::to_string(pl.prune);
     for (const ClassPlan& cp : plan.cls) {
         k += "|" + std::to_string(cp.p) + "," + std::to_string(cp.K) + "," + std::to_string(cp.Kk) + "," +
@@ -568,6 +580,20 @@ td_status setup_call(DeviceCtx* dc, Workspace* w, const Plan& plan, const td_opt
         ++w->generation;
         if (hipMalloc(&w->deferred, (size_t)dcap * sizeof(Deferred)) != hipSuccess) return TD_ERR_OUT_OF_MEMORY;
         w->defer_cap = dcap;
+    }
+    // work items the bucketed sweep may hand to its float64 pass: one entry per
+    // item of the largest class, at most kMaxRedo (past that, the subsets
+    // that need float64 go to the exact tier one by one)
+    uint64_t rcap = 64;
+    for (const ClassPlan& cp : plan.cls) rcap = std::max<uint64_t>(rcap, cp.items);
+    rcap = std::min<uint64_t>(rcap, kMaxRedo);
+    if (w->redo_cap < rcap) {
+        hipFree(w->redo);
+        w->redo = nullptr;
+        w->redo_cap = 0;
+        ++w->generation;
+        if (hipMalloc(&w->redo, (size_t)rcap * sizeof(RedoItem)) != hipSuccess) return TD_ERR_OUT_OF_MEMORY;
+        w->redo_cap = rcap;
     }
     if ((st = grow(w, &w->wscratch, &w->wscratch_cap, plan.scratch)) != TD_OK) return st;
 
@@ -613,6 +639,8 @@ td_status setup_call(DeviceCtx* dc, Workspace* w, const Plan& plan, const td_opt
     pl.deferred = w->deferred;
     pl.ctr = w->ctr;
     pl.defer_cap = (uint64_t)dcap;
+    pl.redo = w->redo;
+    pl.redo_cap = w->redo_cap;
     pl.filter_scale = std::isinf(o.filter_scale) ? 3.0e38f : (float)o.filter_scale;
     pl.force_exact = (o.force_exact || o.precision == TD_PREC_EXACT) ? 1 : 0;
     pl.sweep_mode = o.sweep;
@@ -647,6 +675,7 @@ td_status run(const Problem* probs, int num, const td_options& o, hipStream_t st
     g_last.ctr = w->ctr;
     g_last.qs = w->qs;
     g_last.nq = nq;
+    g_last.redo_cap = pl.redo_cap;
     if (!use_graph) {
         g_last.timing = o.timing ? 1 : 0;
         return enqueue(plan, pl, o, stream, w, o.timing != 0);
@@ -925,6 +954,7 @@ td_status run_adia(const Problem& pr, const td_options& o, hipStream_t stream) {
 // ------------------------------------------------ allocation-free call
 constexpr int kNoAllocMaxDevices = 64;
 constexpr uint64_t kNoAllocDeferCap = 1ull << 18;   // deferred subsets per call
+constexpr uint64_t kNoAllocRedoCap = 1ull << 16;    // work items of the float64 pass
 
 struct NoAllocDev {
     uint8_t* base = nullptr;    // device address of `scratch` on this device
@@ -934,7 +964,7 @@ NoAllocDev g_noalloc[kNoAllocMaxDevices];
 
 // Byte offsets of one call's arrays inside `scratch` (256-byte aligned).
 struct NoAllocLayout {
-    uint64_t ctr, cp, binom, qd, qs, x64, x64lo, x32, xi, nrm, deferred, ws, end;
+    uint64_t ctr, cp, binom, qd, qs, x64, x64lo, x32, xi, nrm, deferred, redo, ws, end;
 };
 
 uint64_t up256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
@@ -954,6 +984,7 @@ NoAllocLayout noalloc_layout(uint64_t m, uint64_t M, uint64_t p, uint64_t ws_byt
     L.xi = o;       o = up256(o + vals * 2 * sizeof(uint64_t));
     L.nrm = o;      o = up256(o + pts * sizeof(float));
     L.deferred = o; o = up256(o + kNoAllocDeferCap * sizeof(Deferred));
+    L.redo = o;     o = up256(o + kNoAllocRedoCap * sizeof(RedoItem));
     L.ws = o;       o = up256(o + ws_bytes);
     L.end = o;
     return L;
@@ -1084,6 +1115,8 @@ td_status run_noalloc(const Problem& pr, const td_options& o, hipStream_t stream
     pl.ctr = reinterpret_cast<Counters*>(b + L.ctr);
     pl.defer_cap = std::min<uint64_t>(kNoAllocDeferCap, o.deferred_capacity > 0 ? (uint64_t)o.deferred_capacity
                                                                                 : kNoAllocDeferCap);
+    pl.redo = reinterpret_cast<RedoItem*>(b + L.redo);
+    pl.redo_cap = kNoAllocRedoCap;
     pl.filter_scale = std::isinf(o.filter_scale) ? 3.0e38f : (float)o.filter_scale;
     pl.force_exact = (o.force_exact || o.precision == TD_PREC_EXACT) ? 1 : 0;
     pl.sweep_mode = o.sweep;
@@ -1114,6 +1147,7 @@ td_status run_noalloc(const Problem& pr, const td_options& o, hipStream_t stream
     g_last.ws = nullptr;
     g_last.device = dev;
     g_last.ctr = pl.ctr;
+    g_last.redo_cap = pl.redo_cap;
     g_last.qs = pl.qs;
     g_last.nq = (int)m;
     g_last.timing = 0;
@@ -1227,6 +1261,7 @@ td_status td_get_stats(td_stats* out) {
     out->exact_subsets = c.exact_done;
     out->adia_evaluations = g_last.adia_evaluations;
     out->adia_candidates = g_last.adia_candidates;
+    for (int k = 0; k < td::kMaxClasses; ++k) out->f64_items += std::min<uint64_t>(c.redo_count[k], g_last.redo_cap);
     std::vector<QueryState> qs(g_last.nq);
     if (g_last.nq > 0) HIPCHK(hipMemcpy(qs.data(), g_last.qs, qs.size() * sizeof(QueryState), hipMemcpyDeviceToHost));
     int dst = 0;

@@ -19,6 +19,8 @@ namespace td {
 constexpr int kDefer = -2;
 constexpr int kSkip = -3;
 constexpr int kFallback = -4;   // bucketed sweep gave up: use the full sort
+constexpr int kNeed64 = -5;     // bucketed sweep needs the float64 basis
+constexpr uint64_t kRedoUnit = 1024;   // subsets per unit of the float64 pass
 constexpr int kBig = 0x7fffffff;
 
 template <int P>
@@ -585,11 +587,16 @@ __device__ __forceinline__ void hist_add32(uint32_t* hist, uint32_t lo, uint32_t
     atomicAdd(&hist[blo], inc);
 }
 
-template <int P, int K>
-__device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
-                            const SlotF64<P>& S64, int nnz, const FiltCtx& fc, uint32_t* hist, uint4* list,
-                            const Staging& sg, int ubound, unsigned long long& rechecks,
-                            unsigned long long& walked) {
+// F64 = false: the sweep without any float64 code (its registers cost the
+// kernel's loop about 12% at p = 5 even where it never runs): where float64
+// is needed it returns kNeed64.  F64 = true: the same sweep with the float64
+// re-check of uncertified points and the float64 re-order of mixed clusters
+// (the float64 pass of the subset kernel).
+template <int P, int K, bool F64>
+__device__ __forceinline__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S, const SlotF64<P>& S64,
+                                            int nnz, const FiltCtx& fc, uint32_t* hist, uint4* list,
+                                            const Staging& sg, int ubound, unsigned long long& rechecks,
+                                            unsigned long long& walked) {
     using G = BucketGeom<K>;
     constexpr int KS = P - 2;
     constexpr int NB = G::NB;
@@ -645,7 +652,8 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     };
     totals();
     // Every point outside I and below nnz that float32 placed is counted; if
-    // fewer than nnz - |I| are, some need the float64 re-check.  Points that
+    // fewer than nnz - |I| are, some need the float64 re-check (F64 only:
+    // otherwise the missing points are left out, as below).  Points that
     // float64 cannot place either (near the fold line, or inside span(x_I))
     // are left out of the sweep; `partial` records it.  Leaving points out
     // lowers every count, and delta_I >= 0, so the bounds of the remaining
@@ -654,7 +662,10 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     uint32_t* wq = sg.pkey + lane * K;
     int* wa = sg.pS + lane * K;
     uint32_t weak = 0;
-    if ((tot & 0x7ff) + ((tot >> 11) & 0x7ff) < nnz - KS) {
+    const bool short32 = (tot & 0x7ff) + ((tot >> 11) & 0x7ff) < nnz - KS;
+    if (!F64) {
+        partial = short32;
+    } else if (short32) {
         // which points: the same evaluation again (from an opaque copy of
         // eps4, so that the compiler does not keep the first evaluation's
         // values live instead); then a float64 re-check with the keys kept in
@@ -726,7 +737,7 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
     // exact tier.  Every lane's bound reaching `ubound` is a wave vote; the
     // minimum itself is reduced only when it is needed.
     if (__all(L >= ubound)) return kSkip;
-    if (partial) return kDefer;
+    if (partial) return F64 ? kDefer : kNeed64;
     L = wave_min_dpp(L);
     // Done when L = U.
     U = wave_min_dpp(U);
@@ -775,8 +786,8 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         // the same keys as the histogram's: float32 again, or the float64
-        // re-check's from the staging arrays
-        // qk: bits of the interval's lower end, aux: its width and the fold
+        // re-check's from the staging arrays; qk: bits of the interval's
+        // lower end, aux: its width and the fold
         if ((weak >> i) & 1u) {
             qk[i] = wq[i];
             aux[i] = (uint32_t)wa[i];
@@ -880,8 +891,10 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
                     s += c - 2 * npos_c;
                 } else if (hp && hn) {
                     // both fold signs inside uncertain order: float64 keys,
-                    // insertion-sorted in the block's staging arrays
+                    // insertion-sorted in the block's staging arrays (with the
+                    // float64 basis only; otherwise the exact tier orders them)
                     if (c > kClusterMax) { defer = 1; break; }
+                    if (!F64) { defer = 2; break; }
                     double* rt = sg.rt;
                     float* rr = sg.rr;
                     bool ok = true;
@@ -948,7 +961,8 @@ __device__ int sweep_bucket(const float (&xr)[K][P], const SlotFilt<P>& S,
         }
     }
     __syncthreads();
-    if (__builtin_amdgcn_readfirstlane(defer)) return kDefer;
+    const int dv = __builtin_amdgcn_readfirstlane(defer);
+    if (dv) return dv == 2 ? kNeed64 : kDefer;
     return min(U, __builtin_amdgcn_readfirstlane(best));
 }
 
@@ -992,7 +1006,11 @@ constexpr int min_waves() {
     return P <= 6 ? 2 : 1;
 }
 
-template <int P, int K, int TIER>
+// REDO = false: the work items of the class in turn.  REDO = true (bucketed
+// sweep, p >= 3): the float64 pass, which finishes the work items that the
+// first pass handed over at a sweep that needed float64 (the float64 basis of
+// every subset kept, sweeps with the float64 code).
+template <int P, int K, int TIER, bool REDO = false>
 __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(Pools pl) {
     constexpr int KS = P - 2;
     constexpr int M = 64 * K;
@@ -1034,9 +1052,38 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
     const int nq = pl.cp->num_queries;
     while (true) {
         unsigned long long item = 0;
-        if (lane == 0) item = cbeg + atomicAdd(&pl.ctr->work_next[pl.cls], 1ull);
-        item = uni64(__shfl(item, 0, 64));
-        if (item >= cend) break;
+        uint64_t rstart = 0;
+        uint64_t rstop = ~0ull;
+        uint64_t rmask = ~0ull;   // subsets of the first batch to sweep
+        if constexpr (REDO) {
+            // the handed-over items (counted by the first pass, which has
+            // completed: the launches are stream-ordered), each cut into
+            // units that the waves take in turn: unit 0 the marked subsets of
+            // the batch at `base`, then kRedoUnit subsets each from base + 64
+            // on, so that no item's rest is left to a single wave
+            const uint64_t upe = 1 + (chunk + kRedoUnit - 1) / kRedoUnit;
+            unsigned long long u = 0;
+            if (lane == 0) u = atomicAdd(&pl.ctr->redo_next[pl.cls], 1ull);
+            u = uni64(__shfl(u, 0, 64));
+            const uint64_t nr = min((uint64_t)pl.ctr->redo_count[pl.cls], pl.redo_cap);
+            const uint64_t e = u / upe;
+            if (e >= nr) break;
+            const uint64_t k = u - e * upe;
+            item = uni64(pl.redo[e].item);
+            const uint64_t base = uni64(pl.redo[e].base);
+            if (k == 0) {
+                rstart = base;
+                rstop = base + 64;
+                rmask = uni64(pl.redo[e].mask);
+            } else {
+                rstart = base + 64 + (k - 1) * kRedoUnit;
+                rstop = rstart + kRedoUnit;
+            }
+        } else {
+            if (lane == 0) item = cbeg + atomicAdd(&pl.ctr->work_next[pl.cls], 1ull);
+            item = uni64(__shfl(item, 0, 64));
+            if (item >= cend) break;
+        }
         const int q = uni(item_query(pl.qd, nq, item));
         const QueryDesc d = pl.qd[q];
         const QueryState st = pl.qs[q];
@@ -1047,8 +1094,9 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
         const int32_t* kmap = d.kmap;
         const int ng = kmap ? uni(d.kcount) : nnz;
         const uint64_t nsub = uni64(binom_lookup(pl.binom, ng, KS));
-        const uint64_t r0 = uni64((item - d.item_begin) * (uint64_t)chunk);
-        const uint64_t r1 = uni64(min(r0 + (uint64_t)chunk, nsub));
+        const uint64_t ib = uni64((item - d.item_begin) * (uint64_t)chunk);
+        const uint64_t r0 = REDO ? rstart : ib;
+        const uint64_t r1 = uni64(min(min(ib + (uint64_t)chunk, nsub), rstop));
         if (r0 >= r1) continue;
         const double* x64 = pl.x64 + d.v_off;
         fc.x64 = x64;
@@ -1071,7 +1119,7 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
             }
             const uint64_t myr = rb + (uint64_t)lane;
             Slot& my = slots[lane];
-            if (myr < r1) {
+            if (myr < r1 && ((rmask >> lane) & 1ull)) {
                 int cc[KS > 0 ? KS : 1];
                 cc[0] = 0;
                 unrank_colex<KS>(pl.binom, myr, ng, cc);
@@ -1109,10 +1157,16 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
                 } else {
                     SlotFilt<P>& S = reinterpret_cast<SlotFilt<P>&>(my);
                     SlotF64<P>& S64 = slots64[lane];
+                    // the float64 basis is kept (in device scratch) only where a
+                    // float64 re-check can read it: the full-sort sweeps and
+                    // the float64 pass
+                    constexpr bool store64 = TIER == kFilt || P == 2 || REDO;
 #pragma unroll
                     for (int c = 0; c < P; ++c) {
-                        S64.e1[c] = Bs.e1[c];
-                        S64.e2[c] = Bs.e2[c];
+                        if (store64) {
+                            S64.e1[c] = Bs.e1[c];
+                            S64.e2[c] = Bs.e2[c];
+                        }
                         S.f1[c] = (float)Bs.e1[c];
                         S.f2[c] = (float)Bs.e2[c];
                     }
@@ -1120,11 +1174,12 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
                     // point and of the basis to float32, p products and sums,
                     // the float64 centring, and the frame error eta
                     S.beta32 = (float)((((double)P + 4.0) * (double)kU32 + 4.0 * kU64 + Bs.eta) * 1.01);
-                    S64.beta64 = (((double)P + 3.0) * kU64 + Bs.eta) * 1.01;
+                    if (store64) S64.beta64 = (((double)P + 3.0) * kU64 + Bs.eta) * 1.01;
                     S.state = (Bs.certified && !pl.force_exact) ? 0 : 3;
                 }
             } else {
-                my.state = 1;
+                // past the item, or (float64 pass) a subset the first pass swept
+                my.state = myr < r1 ? 4 : 1;
             }
             __syncthreads();
             // points of the query in registers for the sweeps of this batch,
@@ -1148,10 +1203,13 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
                 }
             }
             const int cnt = (int)min((uint64_t)64, r1 - rb);
+            // subsets of the batch that need the float64 pass (first pass, p >= 3)
+            uint64_t need = 0;
             for (int s = 0; s < cnt; ++s) {
                 const Slot& S = slots[s];
                 const int sstate = uni(S.state);
                 if (sstate == 1) { ++ninvalid; continue; }
+                if (REDO && sstate == 4) continue;
                 int term;
                 if constexpr (TIER == kPlain) {
                     term = sweep_plain<P, K>(xd, reinterpret_cast<const SlotPlain<P>&>(S), nnz);
@@ -1166,10 +1224,24 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
                             // sweep per query) the full bitonic sort takes
                             // these sweeps, otherwise the exact tier does
                             term = kFallback;
-                            if (nnz - KS <= 1023)
-                                term = sweep_bucket<P, K>(xf, reinterpret_cast<const SlotFilt<P>&>(S), slots64[s],
-                                                          nnz, fc, hist, glist, sg, min(qbest, wbest), rechecks,
-                                                          nwalked);
+                            if (nnz - KS <= 1023) {
+                                const int ub = min(qbest, wbest);
+                                const SlotFilt<P>& SF = reinterpret_cast<const SlotFilt<P>&>(S);
+                                term = sweep_bucket<P, K, REDO>(xf, SF, slots64[s], nnz, fc, hist, glist, sg, ub,
+                                                                rechecks, nwalked);
+                                if (term == kNeed64) {
+                                    if constexpr (P == 2) {
+                                        term = kFallback;   // the full sort has float64
+                                    } else {
+                                        // marked for the float64 pass; no branch
+                                        // out of the loop here (one makes the
+                                        // compiler turn the sweep's loops into
+                                        // exec-masked code: 11% at p = 5)
+                                        need |= 1ull << s;
+                                        continue;
+                                    }
+                                }
+                            }
                             if (term == kFallback) {
                                 if constexpr (P == 2)
                                     term = sweep_filt<P, K>(xf, reinterpret_cast<const SlotFilt<P>&>(S), slots64[s],
@@ -1200,6 +1272,32 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
                 wbest = min(wbest, term);
             }
             __syncthreads();
+            if constexpr (BUCKET && P > 2 && !REDO) {
+                if (need) {
+                    // hand the marked subsets and the rest of the item to the
+                    // float64 pass; with its list full, the marked subsets go
+                    // to the exact tier and the item goes on here
+                    unsigned long long pos = 0;
+                    if (lane == 0) pos = atomicAdd(&pl.ctr->redo_count[pl.cls], 1ull);
+                    pos = uni64(__shfl(pos, 0, 64));
+                    if (pos < pl.redo_cap) {
+                        if (lane == 0) {
+                            RedoItem ri;
+                            ri.item = item;
+                            ri.base = rb;
+                            ri.mask = need;
+                            pl.redo[pos] = ri;
+                        }
+                        break;
+                    }
+                    for (int s = 0; s < 64; ++s) {
+                        if ((need >> s) & 1ull) {
+                            if (lane == 0) push_deferred<P>(pl, q, rb + (uint64_t)s);
+                            ++ndefer;
+                        }
+                    }
+                }
+            }
         }
         if (lane == 0 && wbest < kBig) atomicMin(&pl.qs[q].min_term, wbest);
     }

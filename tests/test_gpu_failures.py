@@ -151,8 +151,12 @@ def test_stress_lattice_certified_and_uncertified(td, dev):
     qs = sorted(g)
     exp = np.array([g[q] for q in qs])
     for sweep in ("auto", "bitonic"):
-        good, _ = run(td, dev, X, Z[qs], sweep=sweep, prune=False)
+        good, st = run(td, dev, X, Z[qs], sweep=sweep, prune=False)
         assert np.array_equal(good, exp), (sweep, good, exp)
+        if sweep == "auto":
+            # the map's condition number leaves float32 uncertified often:
+            # the bucketed kernel hands most work items to its float64 pass
+            assert st["f64_items"] > 0 and st["fp64_rechecks"] > 0, st
         bad, _ = run(td, dev, X, Z[qs], sweep=sweep, prune=False, filter_scale=0.0)
         print(sweep, "stress lattice, filter_scale=0:", bad.tolist(), "expected", exp.tolist(),
               "mismatches", int(np.sum(bad != exp)))
