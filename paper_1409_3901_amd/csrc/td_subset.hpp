@@ -1050,24 +1050,28 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
     const uint64_t cend = pl.cp->cls_end[pl.cls];
     const uint32_t chunk = pl.cp->cls_chunk[pl.cls];
     const int nq = pl.cp->num_queries;
+    // float64 pass: the handed-over items, counted by the first pass (which
+    // has completed: the launches are stream-ordered); none, as a rule, and
+    // then no block touches the shared work counter (4096 atomics on one
+    // address cost about 0.5 ms)
+    const uint64_t nredo = REDO ? uni64(min((uint64_t)pl.ctr->redo_count[pl.cls], pl.redo_cap)) : 0;
+    if (REDO && nredo == 0) return;
     while (true) {
         unsigned long long item = 0;
         uint64_t rstart = 0;
         uint64_t rstop = ~0ull;
         uint64_t rmask = ~0ull;   // subsets of the first batch to sweep
         if constexpr (REDO) {
-            // the handed-over items (counted by the first pass, which has
-            // completed: the launches are stream-ordered), each cut into
-            // units that the waves take in turn: unit 0 the marked subsets of
-            // the batch at `base`, then kRedoUnit subsets each from base + 64
-            // on, so that no item's rest is left to a single wave
+            // each handed-over item cut into units that the waves take in
+            // turn: unit 0 the marked subsets of the batch at `base`, then
+            // kRedoUnit subsets each from base + 64 on, so that no item's
+            // rest is left to a single wave
             const uint64_t upe = 1 + (chunk + kRedoUnit - 1) / kRedoUnit;
             unsigned long long u = 0;
             if (lane == 0) u = atomicAdd(&pl.ctr->redo_next[pl.cls], 1ull);
             u = uni64(__shfl(u, 0, 64));
-            const uint64_t nr = min((uint64_t)pl.ctr->redo_count[pl.cls], pl.redo_cap);
             const uint64_t e = u / upe;
-            if (e >= nr) break;
+            if (e >= nredo) break;
             const uint64_t k = u - e * upe;
             item = uni64(pl.redo[e].item);
             const uint64_t base = uni64(pl.redo[e].base);
