@@ -69,6 +69,10 @@ typedef enum {
                                      inputs exceed 126 bits */
 #define TD_DEV_DEGENERACY_LIMIT 16/* exact fallback met a tie run or an in-span
                                      point set larger than the library handles */
+#define TD_DEV_NOT_GENERAL 32     /* TD_METHOD_VERTEX: a point's side of some
+                                     hyperplane through p-1 points is not
+                                     certified in float64 (points not in
+                                     general position, or too close to it) */
 
 typedef enum {
     TD_PREC_FP64_PLAIN = 0,    /* float64 keys, no certification */
@@ -90,11 +94,11 @@ typedef enum {
 
 /* Which of the paper's algorithms computes the count (td_depth, td_depth_ex
  * only; td_depth_batched and td_depth_noalloc return TD_ERR_UNSUPPORTED for
- * ADIA). */
+ * the methods other than RCOM). */
 typedef enum {
     TD_METHOD_RCOM = 0,   /* Algorithm 1 with Algorithm 2 (Section 3): every
                              (p-2)-subset; the exact count */
-    TD_METHOD_ADIA = 1    /* Algorithm 3 (Section 4): a descent over critical
+    TD_METHOD_ADIA = 1,   /* Algorithm 3 (Section 4): a descent over critical
                              (p-1)-sets by Proposition 3 (Steps 2-4), then
                              Algorithm 1 over the subsets of the candidate
                              points only (Step 5), swept by the certified
@@ -105,6 +109,19 @@ typedef enum {
                              whenever an optimal subset lies among the
                              candidates.  For p < 3 or n <= 2p, Algorithm 1
                              (the paper's advice). */
+    TD_METHOD_VERTEX = 2  /* Proposition 1 with r = p-1 (Section 2, the
+                             critical-direction route): the smaller side count
+                             of every hyperplane through the query and p-1
+                             sample points, O(n^p); an independent check of
+                             RCOM.  Valid for points in general position (the
+                             proposition's assumption): every side decision is
+                             certified in float64 (cofactors with a
+                             permanent-based error bound), and a query with an
+                             undecided one returns -1 with TD_DEV_NOT_GENERAL.
+                             n <= 512 (TD_ERR_UNSUPPORTED beyond); a query
+                             needs n' >= p-1 points apart from it
+                             (TD_DEV_NO_VALID_SUBSET otherwise); p = 1 is the
+                             closed form. */
 } td_method;
 
 typedef struct {

@@ -25,9 +25,9 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported request", 3: "out of d
           7: "call too large for the static workspace"}
 PRECISION = {"plain": 0, "fp64": 0, "filtered": 1, "fp32": 1, "exact": 2}
 SWEEP = {"auto": 0, "bucket": 0, "bitonic": 1}
-METHOD = {"rcom": 0, "adia": 1}
+METHOD = {"rcom": 0, "adia": 1, "vertex": 2}
 DEV_BITS = {1: "nonfinite", 2: "no_valid_subset", 4: "defer_overflow", 8: "exact_range",
-            16: "degeneracy_limit"}
+            16: "degeneracy_limit", 32: "not_general"}
 MAX_P = 8
 MAX_N = 1024
 

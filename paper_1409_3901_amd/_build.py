@@ -11,8 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_lib")
 SO = os.path.join(OUT, "libtd.so")
 SOURCES = ["td_exact_p%d.hip" % p for p in (8, 7, 6, 5, 4, 3, 2)] + [
-    "td_subset_filt.hip", "td_subset_bucket.hip", "td_subset_bucket64.hip", "td_subset_plain.hip", "td_adia.hip", "td_host.hip", "td_prep.hip",
-    "td_exact.hip"]
+    "td_subset_filt.hip", "td_subset_bucket.hip", "td_subset_bucket64.hip", "td_subset_plain.hip", "td_adia.hip",
+    "td_vertex.hip", "td_host.hip", "td_prep.hip", "td_exact.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -7,7 +7,7 @@ namespace td {
 constexpr int kMaxP = 8;
 constexpr int kMaxN = 1024;
 constexpr int kWave = 64;
-constexpr int kBinomK = 7;             // binomial table columns k = 0..6
+constexpr int kBinomK = 8;             // binomial table columns k = 0..7
 constexpr int kBinomN = kMaxN + 2;     // rows n = 0..kMaxN+1
 
 // kFiltBucket: the float32-filtered tier with the bucketed sweep.
@@ -19,6 +19,7 @@ constexpr int kStNoValid = 2;
 constexpr int kStDeferOverflow = 4;
 constexpr int kStExactRange = 8;
 constexpr int kStDegenLimit = 16;
+constexpr int kStNotGeneral = 32;       // vertex check: a side not certified
 // internal: the exact integer copy of this query is unusable
 constexpr int kStNoExactInts = 1 << 8;
 

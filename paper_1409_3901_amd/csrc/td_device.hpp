@@ -24,6 +24,16 @@ __device__ __forceinline__ float unif(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
+// Which query a global work item belongs to (binary search on item_begin).
+__device__ __forceinline__ int item_query(const QueryDesc* qd, int nq, uint64_t item) {
+    int lo = 0, hi = nq - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (qd[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // ------------------------------------------------------------ wave helpers
 template <typename T>
 __device__ __forceinline__ T shfl_xor_t(T v, int mask) {

@@ -31,6 +31,8 @@ extern "C" hipError_t td_launch_subset_plain(int P, int K, int blocks, hipStream
 extern "C" hipError_t td_launch_subset_filt(int P, int K, int blocks, hipStream_t s, const td::Pools* pl);
 extern "C" hipError_t td_launch_subset_bucket(int P, int K, int blocks, hipStream_t s, const td::Pools* pl);
 extern "C" hipError_t td_launch_subset_bucket64(int P, int K, int blocks, hipStream_t s, const td::Pools* pl);
+extern "C" hipError_t td_launch_vertex(int P, int K, int blocks, hipStream_t s, const td::Pools* pl);
+extern "C" int td_resident_blocks_vertex(int P, int K);
 extern "C" int td_resident_blocks_plain(int P, int K);
 extern "C" int td_resident_blocks_filt(int P, int K);
 extern "C" int td_resident_blocks_bucket(int P, int K);
@@ -69,6 +71,7 @@ using td::RedoItem;
 
 constexpr int64_t kDefaultDeferCap = 1 << 25;
 constexpr uint64_t kMaxRedo = 1ull << 22;   // work items of the float64 pass per call
+constexpr int64_t kVertexMaxN = 512;        // the vertex check keeps 8 points per lane
 
 using td::binom_host;
 
@@ -279,7 +282,7 @@ td_status check_options(const td_options& o) {
     if (o.deferred_capacity < 0) return TD_ERR_INVALID_ARG;
     if (o.sweep < 0 || o.sweep > 1) return TD_ERR_INVALID_ARG;
     if (o.prune < 0 || o.prune > 1) return TD_ERR_INVALID_ARG;
-    if (o.method < 0 || o.method > 1) return TD_ERR_INVALID_ARG;
+    if (o.method < 0 || o.method > 2) return TD_ERR_INVALID_ARG;
     return TD_OK;
 }
 
@@ -951,6 +954,68 @@ td_status run_adia(const Problem& pr, const td_options& o, hipStream_t stream) {
     return st;
 }
 
+// ------------------------------------------------ vertex-form check
+// Proposition 1 with r = p - 1: the count from the (p-1)-subsets (one
+// hyperplane each), certified in float64; a query with an undecided side
+// reports TD_DEV_NOT_GENERAL.  Work items are chunks of colex ranks of
+// (p-1)-subsets; n <= 512 (8 points per lane); p = 1 is the closed form of
+// the preparation kernel, as for Algorithm 1.
+td_status run_vertex(const Problem& pr, const td_options& o, hipStream_t stream) {
+    if (pr.p < 2) return run(&pr, 1, o, stream, false);
+    if (pr.n > kVertexMaxN) return TD_ERR_UNSUPPORTED;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return TD_ERR_NO_DEVICE;
+    DeviceCtx* dc = nullptr;
+    td_status st = ensure_device(dev, &dc);
+    if (st != TD_OK) return st;
+    Workspace* w = nullptr;
+    if ((st = get_workspace(dc, dev, stream, &w)) != TD_OK) return st;
+    // the vertex count is its own: no bound from the directions +-x_j
+    td_options po = o;
+    po.prune = 0;
+    Plan plan;
+    if ((st = make_plan(dc, &pr, 1, po, &plan)) != TD_OK) return st;
+    if (plan.qd.empty() || plan.cls.empty()) return TD_OK;
+    // items over the (p-1)-subsets (queries are grouped by class)
+    for (ClassPlan& cp : plan.cls) cp.items = 0;
+    uint64_t item = 0;
+    for (QueryDesc& d : plan.qd) {
+        d.item_begin = item;
+        d.items = 0;
+        if (d.cls < 0) continue;
+        const uint64_t chunk = (uint64_t)plan.cls[d.cls].chunk;
+        const uint64_t it = (binom_host(d.n, d.p - 1) + chunk - 1) / chunk;
+        if (it > 0xffffffffull) return TD_ERR_UNSUPPORTED;
+        d.items = (uint32_t)it;
+        plan.cls[d.cls].items += it;
+        item += it;
+    }
+    Pools pl;
+    if ((st = setup_call(dc, w, plan, po, stream, &pl)) != TD_OK) return st;
+    g_last.adia_evaluations = 0;
+    g_last.adia_candidates = 0;
+    g_last.ws = w;
+    g_last.device = w->device;
+    g_last.ctr = w->ctr;
+    g_last.qs = w->qs;
+    g_last.nq = (int)plan.qd.size();
+    g_last.redo_cap = pl.redo_cap;
+    g_last.timing = 0;
+    HIPCHK(td_launch_init(&pl, stream));
+    HIPCHK(td_launch_prep(&pl, plan.prep_blocks, stream));
+    for (size_t c = 0; c < plan.cls.size(); ++c) {
+        const ClassPlan& cp = plan.cls[c];
+        if (cp.items == 0) continue;
+        Pools pc = pl;
+        pc.cls = (int)c;
+        const int rb = std::max(1, td_resident_blocks_vertex(cp.p, cp.K));
+        const int blocks = (int)std::min<uint64_t>(cp.items, (uint64_t)dc->num_cu * (uint64_t)rb);
+        HIPCHK(td_launch_vertex(cp.p, cp.K, blocks, stream, &pc));
+    }
+    HIPCHK(td_launch_finalize(&pl, plan.fin_blocks, stream));
+    return TD_OK;
+}
+
 // ------------------------------------------------ allocation-free call
 constexpr int kNoAllocMaxDevices = 64;
 constexpr uint64_t kNoAllocDeferCap = 1ull << 18;   // deferred subsets per call
@@ -1192,6 +1257,7 @@ td_status td_depth_ex(const double* X, int64_t n, int32_t p, const double* Z, in
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return TD_ERR_NO_DEVICE;
     if (o.method == TD_METHOD_ADIA) return run_adia(pr, o, (hipStream_t)stream);
+    if (o.method == TD_METHOD_VERTEX) return run_vertex(pr, o, (hipStream_t)stream);
     return run(&pr, 1, o, (hipStream_t)stream, false);
 }
 

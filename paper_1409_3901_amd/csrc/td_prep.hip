@@ -238,7 +238,7 @@ __global__ void finalize_kernel(Pools pl) {
     const int nq = pl.cp->num_queries;
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
         QueryState st = pl.qs[q];
-        int bad = st.status & (kStNonfinite | kStDeferOverflow | kStExactRange | kStDegenLimit);
+        int bad = st.status & (kStNonfinite | kStDeferOverflow | kStExactRange | kStDegenLimit | kStNotGeneral);
         int out;
         if (bad) {
             out = -1;

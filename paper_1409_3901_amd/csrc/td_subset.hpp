@@ -57,16 +57,6 @@ struct Staging {
 // f(S) = min(S, m - S): the smaller side of the line through the origin.
 __device__ __forceinline__ int fside(int s, int m) { return min(s, m - s); }
 
-// Which query a global work item belongs to (binary search on item_begin).
-__device__ __forceinline__ int item_query(const QueryDesc* qd, int nq, uint64_t item) {
-    int lo = 0, hi = nq - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (qd[mid].item_begin <= item) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 // ---------------------------------------------------------------- plain
 template <int P, int K>
 __device__ int sweep_plain(const double (&xr)[K][P], const SlotPlain<P>& S, int nnz) {
