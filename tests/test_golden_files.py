@@ -59,3 +59,19 @@ def test_config_goldens_within_bounds():
         X, Z = workloads.config(cfg)
         for k, v in _load(cfg).items():
             assert 0 <= v <= _bound(X, Z[int(k)]), (cfg, k, v)
+
+
+def test_adia_grid_covered():
+    """adia.json: Algorithm 3's value and candidate count for every case of
+    workloads.ADIA_GRID_CASES, each at or above the exact count where that is
+    stored, and within the bound that holds for any count."""
+    with open(os.path.join(GOLD, "adia.json")) as f:
+        g = json.load(f)
+    for p, n, alpha in workloads.ADIA_GRID_CASES:
+        key = "%d,%d,%.1f" % (p, n, alpha)
+        X, Z = workloads.grid(p, n, alpha)
+        assert key in g["adia"] and key in g["candidates"], key
+        assert 0 <= g["adia"][key] <= _bound(X, Z[0])
+        assert p - 2 <= g["candidates"][key] <= n
+        if key in g["exact"]:
+            assert g["exact"][key] <= g["adia"][key]

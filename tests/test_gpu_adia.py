@@ -102,3 +102,30 @@ def test_adia_unsupported_entry_points(td, dev):
     with pytest.raises(td.TDError) as e:
         td.depth_noalloc(X, Z, out, method="adia")
     assert e.value.code == 2
+
+
+def _adia_golden():
+    with open(os.path.join(GOLD, "adia.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("key", sorted(_adia_golden()["adia"]))
+def test_adia_paper_grid_vs_stored_oracle(td, dev, key):
+    """The paper's simulation design (X ~ N(0, I_p), z = alpha 1_p) at its
+    full sizes: the GPU's Algorithm 3 equals the oracle's Algorithm 3 (value
+    and candidate count, stored by tests/golden/make_golden.py), and where the
+    exact count is stored, RCom equals it.  At p = 6, n = 320, alpha = 0 the
+    adaptive value (111) lies above the exact depth (110): Step 5's candidate
+    union misses every optimal subset there, on both sides."""
+    g = _adia_golden()
+    p, n, alpha = key.split(",")
+    X, Z = workloads.grid(int(p), int(n), float(alpha))
+    print("adia grid", key, flush=True)
+    got, st = run(td, dev, X, Z)
+    assert st["device_status"] == 0
+    assert int(got[0]) == g["adia"][key], (key, got, g["adia"][key])
+    assert st["adia_candidates"] == g["candidates"][key]
+    if key in g["exact"]:
+        rc = td.depth(to_dev(X, dev), to_dev(Z, dev)).cpu().numpy()
+        assert int(rc[0]) == g["exact"][key]
+        assert int(got[0]) >= g["exact"][key]
