@@ -473,7 +473,8 @@ def bench_paper_grid(td, workloads, torch, np, dev):
     """The paper's simulation design (X ~ N(0, I_p), seeded; one query
     z = alpha 1_p) for p = 3..6, n = 40..640 and alpha in {0, 0.4, 0.8, 1.2}:
     the time of one td_depth call by Algorithm 1 (RCom) and by Algorithm 3
-    (ADIA), best of 3 (host clock around the call and a synchronisation; the
+    (ADIA), best of 3, and of one call of the vertex-form check where it is
+    small enough (host clock around the call and a synchronisation; the
     ADIA call synchronises between its steps), the two counts (which must
     agree: the rows report it), ADIA's evaluated subsets and candidate points,
     and the paper's seconds for RCom (Table 2, alpha = 0) and ADIA (Table 3)
@@ -506,16 +507,27 @@ def bench_paper_grid(td, workloads, torch, np, dev):
                         row["adia_evaluations"] = st["adia_evaluations"]
                         row["adia_candidates"] = st["adia_candidates"]
                 row["counts_agree"] = row["rcom_count"] == row["adia_count"]
+                # the vertex-form check (Proposition 1 with r = p - 1, the
+                # critical-direction route), O(n^p): one timed call where the
+                # work is at most 2e11 point-sides
+                row["vertex_ms"] = row["vertex_count"] = None
+                if n <= 512 and math.comb(n, p - 1) * n <= 2e11:
+                    t = time.perf_counter()
+                    c = td.depth(Xd, Zd, method="vertex")
+                    torch.cuda.synchronize()
+                    row["vertex_ms"] = (time.perf_counter() - t) * 1e3
+                    row["vertex_count"] = int(c.cpu()[0])
                 row["paper_rcom_s"] = PAPER_TABLE2_S.get((p, n)) if alpha == 0.0 else None
                 row["paper_adia_s"] = PAPER_TABLE3_S[(p, alpha)][ni]
                 rows.append(row)
-                print("[grid] p=%d n=%d alpha=%.1f rcom %.3f ms adia %.3f ms (%d / %d)"
-                      % (p, n, alpha, row["rcom_ms"], row["adia_ms"], row["rcom_count"], row["adia_count"]),
-                      file=sys.stderr, flush=True)
+                print("[grid] p=%d n=%d alpha=%.1f rcom %.3f ms adia %.3f ms vertex %s ms (%d / %d / %s)"
+                      % (p, n, alpha, row["rcom_ms"], row["adia_ms"], row["vertex_ms"], row["rcom_count"],
+                         row["adia_count"], row["vertex_count"]), file=sys.stderr, flush=True)
     print(json.dumps({"metric": "ms per query on the paper's simulation grid, RCom and ADIA (context)",
                       "unit": "ms", "n_gpus": 1, "data": "synthetic",
                       "paper_hardware": "Intel Core i7-2670QM 2.2 GHz, Matlab 7.8 (Tables 2 and 3)",
                       "all_counts_agree": all(r["counts_agree"] for r in rows),
+                      "vertex_agrees_with_rcom": all(r["vertex_count"] in (None, r["rcom_count"]) for r in rows),
                       "rows": rows}), flush=True)
 
 

@@ -493,6 +493,8 @@ struct DD {
 // floating-point contraction (a*b + c fused into one FMA) is switched off in
 // these helpers, where the compiler would otherwise fuse the product of
 // dd_mul into the sum that follows it.
+// Knuth's TwoSum (The Art of Computer Programming, vol. 2, 4.2.2): s + err =
+// a + b exactly, in six operations and without a branch on the magnitudes.
 __device__ __forceinline__ DD dd_two_sum(double a, double b) {
 #pragma clang fp contract(off)
     const double s = a + b;
@@ -500,8 +502,10 @@ __device__ __forceinline__ DD dd_two_sum(double a, double b) {
     return DD{s, (a - (s - z)) + (b - z)};
 }
 
-// (ah + al) * (x.hi + x.lo): exact leading product by FMA, cross terms
-// rounded, al * x.lo dropped; absolute error <= 5 u^2 |a| |x|
+// (ah + al) * (x.hi + x.lo): the leading product made exact by the FMA-based
+// TwoProduct (p = fl(ah x.hi), e = fma(ah, x.hi, -p); Ogita, Rump and Oishi,
+// 2005), cross terms rounded, al * x.lo dropped; absolute error
+// <= 5 u^2 |a| |x|
 __device__ __forceinline__ DD dd_mul(double ah, double al, DD x) {
 #pragma clang fp contract(off)
     const double p = ah * x.hi;
