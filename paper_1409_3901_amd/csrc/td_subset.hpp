@@ -577,6 +577,16 @@ __device__ __forceinline__ void hist_add32(uint32_t* hist, uint32_t lo, uint32_t
     atomicAdd(&hist[blo], inc);
 }
 
+// A zero made in a vector register where it is used (a volatile move the
+// compiler cannot hoist): the histogram clears otherwise read a zero pair
+// that the register allocator keeps in scratch memory at 14 points per lane,
+// one scratch load and a full memory wait per sweep.
+__device__ __forceinline__ uint32_t vzero() {
+    uint32_t z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    return z;
+}
+
 // F64 = false: the sweep without any float64 code (its registers cost the
 // kernel's loop about 12% at p = 5 even where it never runs): where float64
 // is needed it returns kNeed64.  F64 = true: the same sweep with the float64
@@ -698,7 +708,7 @@ __device__ __forceinline__ int sweep_bucket(const float (&xr)[K][P], const SlotF
         totals();
     }
 #pragma unroll
-    for (int j = 0; j < NBL; ++j) hist[lane * NBL + j] = 0u;
+    for (int j = 0; j < NBL; ++j) hist[lane * NBL + j] = vzero();
     const int pre = incl - (int)tl;
     const int S0 = tot & 0x7ff;
     const int m = S0 + ((tot >> 11) & 0x7ff);
@@ -804,7 +814,7 @@ __device__ __forceinline__ int sweep_bucket(const float (&xr)[K][P], const SlotF
     const int gtot = __builtin_amdgcn_readlane(gincl, 63);
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < NBL; ++j) hist[lane * NBL + j] = 0u;
+    for (int j = 0; j < NBL; ++j) hist[lane * NBL + j] = vzero();
     if (gtot > kListMax) {
         __syncthreads();
         return kFallback;   // too many points to walk: the caller runs the full sort
