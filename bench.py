@@ -93,6 +93,9 @@ def main():
                     help="the paper's simulation grid (X ~ N(0, I_p), z = alpha 1_p, one query), "
                          "Algorithm 1 (RCom) and Algorithm 3 (ADIA) timed per query beside the "
                          "paper's own timings as context")
+    ap.add_argument("--widths", action="store_true",
+                    help="point-steps/s of the bucketed kernel for every points-per-lane width at "
+                         "p = 5 (one law, queries inside the hull, no pruning)")
     ap.add_argument("--p2", action="store_true",
                     help="p = 2, n = 1024, m = 1024 queries: one sweep per query (Algorithm 2 "
                          "alone), filtered and plain tiers, against stored oracle counts")
@@ -131,6 +134,8 @@ def main():
         return bench_paper_grid(td, workloads, torch, np, dev)
     if a.every_point:
         return bench_every_point(td, workloads, torch, np, dev)
+    if a.widths:
+        return bench_widths(td, torch, np, dev)
     if a.p2:
         return bench_p2(a, td, workloads, torch, np, dev)
     if a.all_configs:
@@ -467,6 +472,46 @@ PAPER_TABLE3_S = {
     (6, 0.8): [0.1638, 0.2295, 62.8009, 158.7744, 1777.3669], (6, 1.2): [1.1149, 3.0121, 1.4400, 4.9680, 19.3288],
 }
 GRID_N = [40, 80, 160, 320, 640]
+
+
+def bench_widths(td, torch, np, dev):
+    """The first-pass bucketed kernel at every points-per-lane width of p = 5
+    (n = 500, 512: 8; 600, 640: 10; 700, 768: 12; 800, 896: 14; 960, 1024:
+    16) on one law, X ~ N(0, I_5), with 8 queries drawn inside the hull
+    (0.2 N(0, I_5)) and pruning off, so that every class sweeps every subset
+    of the same kind of query: subset-stage time (the library's events, best
+    of 3) and point-steps/s over the real points.  The per-class rates of the
+    batched workload mix in how fast each class's queries settle under the
+    pruning bound and how much padding the class carries."""
+    rng = np.random.default_rng(11)
+    rows = []
+    for n in (500, 512, 600, 640, 700, 768, 800, 896, 960, 1024):
+        X = rng.standard_normal((n, 5))
+        Z = 0.2 * rng.standard_normal((8, 5))
+        Xd = torch.tensor(X, device=dev)
+        Zd = torch.tensor(Z, device=dev)
+        td.autotune(5, n)
+        td.depth(Xd, Zd, prune=False)
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(3):
+            td.depth(Xd, Zd, prune=False, timing=True)
+            torch.cuda.synchronize()
+            st = td.get_stats()
+            best = st["subset_ms"] if best is None else min(best, st["subset_ms"])
+        k = max(64, 1 << (n - 1).bit_length()) // 64
+        if k == 16 and n <= 896:
+            k = (n + 127) // 128 * 2
+        sub = 8 * math.comb(n, 3)
+        rows.append({"n": n, "points_per_lane": k, "subset_ms": best, "sweeps_per_s": sub / (best / 1e3),
+                     "point_steps_per_s": sub * (n - 3) / (best / 1e3),
+                     "slot_steps_per_s": sub * 64 * k / (best / 1e3),
+                     "walked_per_sweep": st["walked_sweeps"] / sub, "deferred_subsets": st["deferred_subsets"],
+                     "f64_items": st["f64_items"], "device_status": st["device_status"]})
+        print("[widths] n=%d K=%d %.1f ms %.3g point-steps/s" % (n, k, best, rows[-1]["point_steps_per_s"]),
+              file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "point-steps/s by points per lane (p = 5, one law, no pruning)",
+                      "unit": "point-steps/s", "n_gpus": 1, "data": "synthetic", "rows": rows}), flush=True)
 
 
 def bench_paper_grid(td, workloads, torch, np, dev):
