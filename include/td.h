@@ -160,7 +160,10 @@ typedef struct {
     uint64_t deferred_subsets;   /* subsets sent to the exact tier */
     uint64_t exact_predicates;   /* exact integer predicates evaluated */
     uint64_t degenerate_subsets; /* subsets with extra points inside span(x_I) */
-    uint64_t invalid_subsets;    /* subsets with linearly dependent points */
+    uint64_t invalid_subsets;    /* subsets with linearly dependent points:
+                                    found by the plain tier's basis, or by
+                                    the exact tier among the deferred
+                                    subsets (then also in deferred_subsets) */
     int32_t device_status;       /* OR of TD_DEV_* over the last call's queries */
     float prep_ms, subset_ms, exact_ms, finalize_ms, total_ms; /* if timing */
     uint64_t walked_sweeps;      /* bucketed sweeps whose bucket bounds did not

@@ -1116,7 +1116,12 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
                 qbest = uni(__hip_atomic_load(&pl.qs[q].min_term, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
                 // a term of 0 cannot be lowered: the rest of the item is not needed
                 if (pl.prune && min(qbest, wbest) == 0) {
-                    if (lane == 0) atomicAdd(&pl.ctr->pruned, (unsigned long long)(r1 - rb));
+                    // subsets left: the rest of the range, or (float64 pass,
+                    // first unit) the marked subsets of its single batch
+                    unsigned long long left = r1 - rb;
+                    if (REDO && rmask != ~0ull)
+                        left = __popcll(rmask & (r1 - rb >= 64 ? ~0ull : (1ull << (r1 - rb)) - 1ull));
+                    if (lane == 0) atomicAdd(&pl.ctr->pruned, left);
                     break;
                 }
                 if constexpr (BUCKET) qbest = min(qbest, uni(st.ub_term));

@@ -8,6 +8,7 @@ decisions trusted without their error bound) must show that the parity
 checks can fail: on exactly degenerate data it has to give wrong counts.
 """
 import json
+import math
 import os
 
 import numpy as np
@@ -180,3 +181,27 @@ def test_negative_control_ray_duplicated(td, dev, sweep, prune):
         wrong += int(bad[0] != exp[0])
     print("uncertified mismatches:", wrong, "of 20")
     assert wrong >= 1
+
+
+def test_float64_pass_accounts_every_subset_once(td, dev):
+    """The mapped lattice sends most work items of the bucketed kernel to its
+    float64 pass (the first pass hands over the marked subsets of a batch and
+    the rest of the item, which the pass cuts into units shared by all
+    waves).  Without pruning, every subset is still swept or deferred exactly
+    once: the two counters add up to sum_q C(n'_q, p-2) (the invalid subsets
+    of the filtered tier are deferred ones the exact tier found dependent)."""
+    X, Z = workloads.c5()
+    g = _c5_golden()
+    qs = sorted(g)[:6]
+    got, st = run(td, dev, X, Z[qs], prune=False)
+    assert np.array_equal(got, [g[q] for q in qs]), got
+    assert st["f64_items"] > 100, st
+    total = sum(math.comb(int(np.sum(~np.all(X == Z[q], axis=1))), X.shape[1] - 2) for q in qs)
+    assert st["subsets_swept"] + st["deferred_subsets"] == total, (st, total)
+    assert st["invalid_subsets"] <= st["deferred_subsets"]
+    # with pruning, the subsets skipped once a minimum reached 0 (counted in
+    # both passes) complete the account
+    got, st = run(td, dev, X, Z[qs])
+    assert np.array_equal(got, [g[q] for q in qs]), got
+    acc = st["subsets_swept"] + st["pruned_subsets"] + st["deferred_subsets"]
+    assert acc == total, (st, total)
