@@ -256,6 +256,17 @@ td_status td_get_stats(td_stats* out);
  * fastest for later calls with autotune = 1; synchronises the device. */
 td_status td_autotune(int32_t p, int64_t n, const td_options* base, void* stream);
 
+/* The cache of td_autotune outlives the process only through these two
+ * calls.  td_tuning_save writes the current device's tuned launch shapes to
+ * the text file `path` (one line per (tier, p, points per lane): chunk and
+ * grid); TD_ERR_INVALID_ARG when the file cannot be written.  td_tuning_load
+ * reads such a file into the current device's cache: every line is checked
+ * before any is applied (TD_ERR_INVALID_ARG for a missing or malformed
+ * file), and a file written on a device with another number of compute
+ * units returns TD_ERR_UNSUPPORTED. */
+td_status td_tuning_save(const char* path);
+td_status td_tuning_load(const char* path);
+
 const char* td_status_string(td_status s);
 
 /* Frees the workspace of every device (safe to call more than once). */

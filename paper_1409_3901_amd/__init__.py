@@ -84,7 +84,8 @@ class Problem(ctypes.Structure):
 
 # exported symbols of include/td.h
 SYMBOLS = ["td_default_options", "td_depth", "td_depth_ex", "td_depth_batched", "td_depth_noalloc",
-           "td_get_stats", "td_autotune", "td_status_string", "td_release", "td_version"]
+           "td_get_stats", "td_autotune", "td_tuning_save", "td_tuning_load", "td_status_string", "td_release",
+           "td_version"]
 
 _lib = None
 
@@ -121,6 +122,10 @@ def load():
     lib.td_get_stats.restype = ctypes.c_int
     lib.td_autotune.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(Options), vp]
     lib.td_autotune.restype = ctypes.c_int
+    lib.td_tuning_save.argtypes = [ctypes.c_char_p]
+    lib.td_tuning_save.restype = ctypes.c_int
+    lib.td_tuning_load.argtypes = [ctypes.c_char_p]
+    lib.td_tuning_load.restype = ctypes.c_int
     lib.td_status_string.argtypes = [ctypes.c_int]
     lib.td_status_string.restype = ctypes.c_char_p
     lib.td_release.argtypes = []
@@ -251,6 +256,21 @@ def autotune(p: int, n: int, stream=None, **opts):
     rc = lib.td_autotune(int(p), int(n), ctypes.byref(o), _stream_ptr(stream))
     if rc != TD_OK:
         raise TDError(rc, "td_autotune")
+
+
+def tuning_save(path: str):
+    """Write the current device's tuned launch shapes to a text file."""
+    rc = load().td_tuning_save(os.fsencode(path))
+    if rc != TD_OK:
+        raise TDError(rc, "td_tuning_save")
+
+
+def tuning_load(path: str):
+    """Read launch shapes written by tuning_save into the current device's
+    cache (the file must come from a device with the same CU count)."""
+    rc = load().td_tuning_load(os.fsencode(path))
+    if rc != TD_OK:
+        raise TDError(rc, "td_tuning_load")
 
 
 def release():

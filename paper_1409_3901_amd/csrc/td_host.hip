@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -1429,6 +1430,61 @@ td_status td_autotune(int32_t p, int64_t n, const td_options* base, void* stream
     st = ensure_device(dev, &dctx);
     if (st != TD_OK) return st;
     dctx->tuned[tune_key(tier, p, K)] = bs;
+    return TD_OK;
+}
+
+td_status td_tuning_save(const char* path) {
+    if (!path) return TD_ERR_INVALID_ARG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return TD_ERR_NO_DEVICE;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceCtx* dc = nullptr;
+    td_status st = ensure_device(dev, &dc);
+    if (st != TD_OK) return st;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return TD_ERR_INVALID_ARG;
+    bool ok = std::fprintf(f, "td-tuning 1\nnum_cu %d\n", dc->num_cu) > 0;
+    for (const auto& kv : dc->tuned) {
+        int tier = 0, p = 0, K = 0;
+        if (std::sscanf(kv.first.c_str(), "%d:%d:%d", &tier, &p, &K) != 3) continue;
+        ok = ok && std::fprintf(f, "%d %d %d %d %d\n", tier, p, K, kv.second.chunk, kv.second.blocks) > 0;
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? TD_OK : TD_ERR_INVALID_ARG;
+}
+
+td_status td_tuning_load(const char* path) {
+    if (!path) return TD_ERR_INVALID_ARG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return TD_ERR_NO_DEVICE;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return TD_ERR_INVALID_ARG;
+    int version = 0, ncu = 0;
+    bool ok = std::fscanf(f, " td-tuning %d num_cu %d", &version, &ncu) == 2 && version == 1 && ncu > 0;
+    std::vector<std::pair<std::string, Shape>> rows;
+    while (ok) {
+        int tier = 0, p = 0, K = 0, chunk = 0, blocks = 0;
+        const int r = std::fscanf(f, "%d %d %d %d %d", &tier, &p, &K, &chunk, &blocks);
+        if (r == EOF) break;
+        const bool kok = K == 1 || K == 2 || K == 4 || K == 8 || K == 10 || K == 12 || K == 14 || K == 16;
+        ok = r == 5 && (tier == td::kPlain || tier == td::kFilt || tier == td::kFiltBucket) && p >= 2 &&
+             p <= TD_MAX_P && kok && chunk >= 64 && chunk <= (1 << 20) && chunk % 64 == 0 && blocks >= 1 &&
+             blocks <= (1 << 20);
+        if (ok) {
+            Shape sh;
+            sh.chunk = chunk;
+            sh.blocks = blocks;
+            rows.emplace_back(tune_key(tier, p, K), sh);
+        }
+    }
+    std::fclose(f);
+    if (!ok) return TD_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceCtx* dc = nullptr;
+    td_status st = ensure_device(dev, &dc);
+    if (st != TD_OK) return st;
+    if (ncu != dc->num_cu) return TD_ERR_UNSUPPORTED;
+    for (const auto& r : rows) dc->tuned[r.first] = r.second;
     return TD_OK;
 }
 

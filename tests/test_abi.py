@@ -72,6 +72,9 @@ def test_invalid_arguments_rejected_without_device(lib):
     assert lib.td_depth(fake, 10, 3, fake, -1, fake, nul) == 1
     # m = 0 is a no-op
     assert lib.td_depth(fake, 10, 3, fake, 0, fake, nul) == 0
+    # the tuning file calls reject a null path before touching a device
+    assert lib.td_tuning_save(None) == 1
+    assert lib.td_tuning_load(None) == 1
     # bad options
     bad = td.Options()
     lib.td_default_options(ctypes.byref(bad))
