@@ -118,7 +118,8 @@ typedef enum {
                              certified in float64 (cofactors with a
                              permanent-based error bound), and a query with an
                              undecided one returns -1 with TD_DEV_NOT_GENERAL.
-                             n <= 512 (TD_ERR_UNSUPPORTED beyond); a query
+                             n <= 512 at p >= 5, n <= 1024 at p <= 4
+                             (TD_ERR_UNSUPPORTED beyond); a query
                              needs n' >= p-1 points apart from it
                              (TD_DEV_NO_VALID_SUBSET otherwise); p = 1 is the
                              closed form. */

@@ -72,7 +72,7 @@ using td::RedoItem;
 
 constexpr int64_t kDefaultDeferCap = 1 << 25;
 constexpr uint64_t kMaxRedo = 1ull << 22;   // work items of the float64 pass per call
-constexpr int64_t kVertexMaxN = 512;        // the vertex check keeps 8 points per lane
+constexpr int64_t kVertexMaxN = 512;        // the vertex check at p >= 5 keeps 8 points per lane
 
 using td::binom_host;
 
@@ -959,11 +959,11 @@ td_status run_adia(const Problem& pr, const td_options& o, hipStream_t stream) {
 // Proposition 1 with r = p - 1: the count from the (p-1)-subsets (one
 // hyperplane each), certified in float64; a query with an undecided side
 // reports TD_DEV_NOT_GENERAL.  Work items are chunks of colex ranks of
-// (p-1)-subsets; n <= 512 (8 points per lane); p = 1 is the closed form of
-// the preparation kernel, as for Algorithm 1.
+// (p-1)-subsets; n <= 512 (8 points per lane), or n <= 1024 at p <= 4 (16);
+// p = 1 is the closed form of the preparation kernel, as for Algorithm 1.
 td_status run_vertex(const Problem& pr, const td_options& o, hipStream_t stream) {
     if (pr.p < 2) return run(&pr, 1, o, stream, false);
-    if (pr.n > kVertexMaxN) return TD_ERR_UNSUPPORTED;
+    if (pr.n > (pr.p <= 4 ? (int64_t)TD_MAX_N : kVertexMaxN)) return TD_ERR_UNSUPPORTED;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return TD_ERR_NO_DEVICE;
     DeviceCtx* dc = nullptr;

@@ -4,7 +4,7 @@
 // query): every lane builds the cofactors of one subset of a batch of 64,
 // then the wave counts the sides of every point of the query for each of
 // them.  No scratch buffers: the subsets' cofactors live in LDS, the points
-// (8 per lane at most: n <= 512) in registers.
+// in registers (8 per lane, n <= 512; 16 per lane, n <= 1024, at p <= 4).
 #include <hip/hip_runtime.h>
 
 #include "td_device.hpp"
@@ -132,6 +132,9 @@ KernelFn pick_k(int K) {
         case 2: return td::vertex_kernel<P, 2>;
         case 4: return td::vertex_kernel<P, 4>;
         case 8: return td::vertex_kernel<P, 8>;
+        case 16:
+            if constexpr (P <= 4) return td::vertex_kernel<P, 16>;
+            return nullptr;
     }
     return nullptr;
 }

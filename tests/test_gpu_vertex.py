@@ -9,6 +9,7 @@ import os
 
 import numpy as np
 import pytest
+import torch
 
 import oracle
 import workloads
@@ -52,6 +53,17 @@ def test_vertex_general_position_vs_oracle_and_rcom(td, dev, p, n):
     assert np.array_equal(got, rcom)
 
 
+@pytest.mark.parametrize("p,n", [(3, 700), (4, 600), (2, 1024)])
+def test_vertex_sixteen_points_per_lane(td, dev, p, n):
+    """n > 512 at p <= 4: 16 points per lane."""
+    rng = np.random.default_rng(960 + p)
+    X = rng.standard_normal((n, p))
+    Z = np.vstack([0.2 * rng.standard_normal((2, p)), X[:1]])
+    got, st = run(td, dev, X, Z)
+    assert st["device_status"] == 0, st
+    assert np.array_equal(got, oracle.depth_counts(X, Z)), got
+
+
 def test_vertex_c3_queries(td, dev):
     X, Z = workloads.c3()
     g = json.load(open(os.path.join(GOLD, "c3.json")))["counts"]
@@ -89,12 +101,17 @@ def test_vertex_limits_and_statuses(td, dev):
     got, st = run(td, dev, X, Z)
     assert got[1] == -1 and "nonfinite" in st["device_status_bits"]
     assert got[0] == oracle.depth_counts(X, Z[:1])[0]
-    # n above 512 is not supported by the check
-    X = rng.standard_normal((600, 3))
+    # n above 512 is not supported by the check at p >= 5
+    X = rng.standard_normal((600, 5))
     with pytest.raises(td.TDError) as e:
-        run(td, dev, X, np.zeros((1, 3)))
+        run(td, dev, X, np.zeros((1, 5)))
     assert e.value.code == 2
     # nor by the batched and allocation-free entry points
-    Xd, Zd = to_dev(X[:100], dev), to_dev(np.zeros((1, 3)), dev)
-    with pytest.raises(td.TDError):
+    Xd, Zd = to_dev(X[:100], dev), to_dev(np.zeros((1, 5)), dev)
+    with pytest.raises(td.TDError) as e:
         td.depth_batched([(Xd, Zd)], method="vertex")
+    assert e.value.code == 2
+    out = torch.zeros(1, dtype=torch.int32, device=Xd.device)
+    with pytest.raises(td.TDError) as e:
+        td.depth_noalloc(Xd, Zd, out, method="vertex")
+    assert e.value.code == 2
