@@ -556,7 +556,7 @@ def bench_paper_grid(td, workloads, torch, np, dev):
                 # critical-direction route), O(n^p): one timed call where the
                 # work is at most 2e11 point-sides
                 row["vertex_ms"] = row["vertex_count"] = None
-                if n <= 512 and math.comb(n, p - 1) * n <= 2e11:
+                if (n <= 512 or p <= 4) and math.comb(n, p - 1) * n <= 2e11:
                     t = time.perf_counter()
                     c = td.depth(Xd, Zd, method="vertex")
                     torch.cuda.synchronize()
