@@ -709,6 +709,18 @@ __device__ __forceinline__ int sweep_bucket(const float (&xr)[K][P], const SlotF
     }
 #pragma unroll
     for (int j = 0; j < NBL; ++j) hist[lane * NBL + j] = vzero();
+    if constexpr (P == 2) {
+        // 1024 points in one sweep: a bucket's crossing field (10 bits)
+        // overflows only if the bucket holds them all; that sweep goes to
+        // the full sort (the pos and neg fields hold up to 2047)
+        bool full = false;
+#pragma unroll
+        for (int j = 0; j < NBL; ++j) full = full || (int)((w[j] & 0x7ffu) + ((w[j] >> 11) & 0x7ffu)) >= 1024;
+        if (__any(full)) {
+            __syncthreads();
+            return kFallback;
+        }
+    }
     const int pre = incl - (int)tl;
     const int S0 = tot & 0x7ff;
     const int m = S0 + ((tot >> 11) & 0x7ff);
@@ -1227,13 +1239,14 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
                         term = kDefer;
                     } else {
                         if constexpr (BUCKET) {
-                            // bucket words count at most 1023 points per field
-                            // (p = 2 with 1024 points in the sweep), and a walk
-                            // gathers at most kListMax points: at p = 2 (one
-                            // sweep per query) the full bitonic sort takes
-                            // these sweeps, otherwise the exact tier does
+                            // a walk gathers at most kListMax points, and a
+                            // bucket's crossing field counts at most 1023: at
+                            // p = 2 (one sweep per query) the full bitonic sort
+                            // takes the sweeps that exceed them, otherwise the
+                            // exact tier does (n <= 1024: at p >= 3 a sweep has
+                            // at most 1023 points)
                             term = kFallback;
-                            if (nnz - KS <= 1023) {
+                            if (nnz - KS <= 1024) {
                                 const int ub = min(qbest, wbest);
                                 const SlotFilt<P>& SF = reinterpret_cast<const SlotFilt<P>&>(S);
                                 term = sweep_bucket<P, K, REDO>(xf, SF, slots64[s], nnz, fc, hist, glist, sg, ub,
