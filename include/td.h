@@ -262,9 +262,10 @@ td_status td_autotune(int32_t p, int64_t n, const td_options* base, void* stream
  * the text file `path` (one line per (tier, p, points per lane): chunk and
  * grid); TD_ERR_INVALID_ARG when the file cannot be written.  td_tuning_load
  * reads such a file into the current device's cache: every line is checked
- * before any is applied (TD_ERR_INVALID_ARG for a missing or malformed
- * file), and a file written on a device with another number of compute
- * units returns TD_ERR_UNSUPPORTED. */
+ * before any is applied and before any device is touched
+ * (TD_ERR_INVALID_ARG for a missing or malformed file), and a file written
+ * on a device with another number of compute units returns
+ * TD_ERR_UNSUPPORTED. */
 td_status td_tuning_save(const char* path);
 td_status td_tuning_load(const char* path);
 

@@ -1455,8 +1455,7 @@ td_status td_tuning_save(const char* path) {
 
 td_status td_tuning_load(const char* path) {
     if (!path) return TD_ERR_INVALID_ARG;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return TD_ERR_NO_DEVICE;
+    // the file is checked before any device is touched
     FILE* f = std::fopen(path, "r");
     if (!f) return TD_ERR_INVALID_ARG;
     int version = 0, ncu = 0;
@@ -1479,6 +1478,8 @@ td_status td_tuning_load(const char* path) {
     }
     std::fclose(f);
     if (!ok) return TD_ERR_INVALID_ARG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return TD_ERR_NO_DEVICE;
     std::lock_guard<std::mutex> lk(g_mu);
     DeviceCtx* dc = nullptr;
     td_status st = ensure_device(dev, &dc);

@@ -72,9 +72,19 @@ def test_invalid_arguments_rejected_without_device(lib):
     assert lib.td_depth(fake, 10, 3, fake, -1, fake, nul) == 1
     # m = 0 is a no-op
     assert lib.td_depth(fake, 10, 3, fake, 0, fake, nul) == 0
-    # the tuning file calls reject a null path before touching a device
+    # the tuning file calls reject a null path, and a missing or malformed
+    # file, before touching a device
     assert lib.td_tuning_save(None) == 1
     assert lib.td_tuning_load(None) == 1
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        assert lib.td_tuning_load(os.path.join(d, "missing.txt").encode()) == 1
+        for text in ("tuning 1\nnum_cu 256\n", "td-tuning 1\nnum_cu 256\n3 4 8 100 64\n",
+                     "td-tuning 1\nnum_cu 256\n3 4 9 256 64\n", "td-tuning 2\nnum_cu 256\n"):
+            f = os.path.join(d, "bad.txt")
+            with open(f, "w") as fh:
+                fh.write(text)
+            assert lib.td_tuning_load(f.encode()) == 1, text
     # bad options
     bad = td.Options()
     lib.td_default_options(ctypes.byref(bad))
