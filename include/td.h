@@ -241,8 +241,11 @@ td_status td_depth_batched(const td_problem* probs, int32_t num, const td_option
  * shrunk to fit the array; a call that does not fit even so (roughly
  * m * M * p * 36 bytes of per-query arrays, M the sort width >= n, plus the
  * deferred list and per-block scratch) returns TD_ERR_TOO_LARGE.  At most
- * 2^18 subsets per call go to the exact tier (deferred_capacity is capped
- * there); beyond that the query reports TD_DEV_DEFER_OVERFLOW.  The tuned
+ * 2^16 work items go to the float64 pass (marked subsets beyond that go to
+ * the exact tier) and at most 2^18 subsets per call to the exact tier
+ * (deferred_capacity is capped there); beyond that the query reports
+ * TD_DEV_DEFER_OVERFLOW, which data far from general position can reach
+ * (the td_depth_ex lists are 2^22 and 2^25 entries).  The tuned
  * launch shapes of td_autotune and the timing option are not used; counters
  * are available from td_get_stats.  Arguments and errors otherwise as
  * td_depth_ex. */
