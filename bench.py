@@ -390,8 +390,9 @@ def _stored_counts(cfg):
 
 def bench_all_configs(td, workloads, torch, np, dev):
     """Each workload through the filtered tier (bucketed sweep) and the plain
-    float64 tier, against the stored oracle counts: mismatches (0 required of
-    the filtered tier; the plain tier's are reported), float64 re-checks and
+    float64 tier, against the stored oracle counts (and the vertex check on
+    c1 and four c3 queries): mismatches (0 required of the filtered tier; the
+    plain tier's are reported), float64 re-checks and
     deferred subsets per sweep, the HIP-event time of the call, and the
     subset kernel's roofline fraction (algorithmic lane-ops of the processed
     subsets over its duration, against the non-packed 32-bit lane-op peak)."""
@@ -444,6 +445,24 @@ def bench_all_configs(td, workloads, torch, np, dev):
     got = np.concatenate([o.cpu().numpy() for o in outs])
     out["c4_subsample"] = {"filtered_batched": {"queries": len(exp),
                                                 "mismatches": int(np.sum(got != np.array(exp)))}}
+    # the vertex-form check (Proposition 1, r = p - 1) beside the stored
+    # counts, where its O(n^p) work is small: c1, and four c3 queries
+    for cfg, qs in (("c1", None), ("c3", [0, 7, 16, 25])):
+        X, Z = workloads.config(cfg)
+        g = _stored_counts(cfg)
+        idx = qs if qs is not None else sorted(int(k) for k in g)
+        Xd = torch.from_numpy(X).to(dev)
+        Zd = torch.from_numpy(np.ascontiguousarray(Z[idx])).to(dev)
+        t = time.perf_counter()
+        c = td.depth(Xd, Zd, method="vertex")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        st = td.get_stats()
+        got = c.cpu().numpy()
+        out[cfg]["vertex"] = {"queries": len(idx), "mismatches": int(np.sum(got != np.array([g[str(q)] for q in idx]))),
+                              "declined": int(np.sum(got == -1)), "s": dt,
+                              "hyperplanes_per_s": st["subsets_swept"] / dt}
+        print("[configs] %s vertex done" % cfg, file=sys.stderr, flush=True)
     print(json.dumps({"metric": "mismatches against the oracle and fallback rates, every workload",
                       "n_gpus": 1, "data": "synthetic", "configs": out}), flush=True)
 
