@@ -1395,9 +1395,9 @@ td_status td_autotune(int32_t p, int64_t n, const td_options* base, void* stream
     const int K = kernel_k(tier, p, n, std::max(64, next_pow2((int)n)) / 64);
     float best = 1e30f;
     Shape bs;
-    const int chunks[] = {64, 128, 256, 512};
+    const int chunks[] = {64, 128, 256, 512, 1024};
     const int grids[] = {4, 8, 12, 16};   // resident waves per CU: up to 3 per SIMD
-    for (int ci = 0; ci < 4 && ret == TD_OK; ++ci)
+    for (int ci = 0; ci < (int)(sizeof(chunks) / sizeof(chunks[0])) && ret == TD_OK; ++ci)
         for (int gi = 0; gi < 4 && ret == TD_OK; ++gi) {
             td_options t = o;
             t.autotune = 0;
