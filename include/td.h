@@ -175,8 +175,11 @@ typedef struct {
     uint64_t exact_subsets;      /* deferred subsets the exact tier took up:
                                     each deferred subset once, so this equals
                                     min(deferred_subsets, deferred_capacity) */
-    uint64_t adia_evaluations;   /* TD_METHOD_ADIA: subsets evaluated in the
-                                    descent (Algorithm 3, Steps 2-4) */
+    uint64_t adia_evaluations;   /* TD_METHOD_ADIA: subsets evaluated on the
+                                    device in the descent (Algorithm 3, Steps
+                                    2-4), counting those of nodes taken off
+                                    the queue ahead in a batch and then
+                                    deleted by an earlier node */
     uint64_t adia_candidates;    /* TD_METHOD_ADIA: candidate points of Step 5,
                                     summed over the queries */
     uint64_t f64_items;          /* work items of the bucketed sweep (p >= 3)

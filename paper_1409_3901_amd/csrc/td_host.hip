@@ -733,7 +733,7 @@ td_status run(const Problem* probs, int num, const td_options& o, hipStream_t st
 // order of the added point; the seed point of Step 2(c) is the smallest
 // index next to a minimising state; Step 5's candidates also hold the points
 // of the subset that attained d0 in Step 4.
-constexpr size_t kAdiaBatch = 64;
+constexpr size_t kAdiaBatch = 256;
 
 td_status adia_eval(Workspace* w, const Pools& pl, int P, int K, const std::vector<td::AdiaJob>& jobs,
                     std::vector<td::AdiaRes>& res, hipStream_t s) {
@@ -856,7 +856,6 @@ td_status run_adia(const Problem& pr, const td_options& o, hipStream_t stream) {
                         if (c != r) j.idx[c2++] = F[(size_t)c];
                     jobs.push_back(j);
                 }
-                qr.evals += (uint64_t)ks + 1;
                 popped[(size_t)q].push_back(F);
             }
         }
@@ -874,6 +873,7 @@ td_status run_adia(const Problem& pr, const td_options& o, hipStream_t stream) {
                 const size_t base = e0;
                 e0 += (size_t)ks + 1;
                 if (!qr.Q.count(F)) continue;   // deleted by an earlier node: not popped
+                qr.evals += (uint64_t)ks + 1;   // the descent's own work (not the speculation)
                 for (int r = 0; r < ks + 1; ++r) {
                     const td::AdiaRes& rr = res[base + (size_t)r];
                     if (rr.term < 0) continue;
