@@ -29,6 +29,7 @@ __global__ __launch_bounds__(256) void prep_kernel(Pools pl) {
     __shared__ int s_pos[kMaxN];
     __shared__ float s_x[kMaxN * kMaxP];
     __shared__ int s_red[8];
+    __shared__ int s_wsum[4];
     __shared__ int s_q;
     __shared__ double s_z[kMaxP];
     const int tid = threadIdx.x;
@@ -95,14 +96,34 @@ __global__ __launch_bounds__(256) void prep_kernel(Pools pl) {
             __syncthreads();
             emax = s_red[2];
         }
-        // order-preserving compaction: scan of the flags
-        if (tid == 0) {
-            int acc = 0;
-            for (int i = 0; i < n; ++i) { s_pos[i] = acc; acc += s_flag[i]; }
-            s_red[3] = acc;
+        // order-preserving compaction: exclusive scan of the flags, four
+        // consecutive flags per thread (n <= kMaxN = 4 * blockDim.x)
+        int nnz = 0;
+        {
+            constexpr int kPer = kMaxN / 256;
+            const int b0 = tid * kPer;
+            int f[kPer];
+            int sum = 0;
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                f[k] = b0 + k < n ? s_flag[b0 + k] : 0;
+                sum += f[k];
+            }
+            const int ex = wave_excl_sum(sum);
+            if ((tid & 63) == 63) s_wsum[tid >> 6] = ex + sum;
+            __syncthreads();
+            int acc = ex;
+            for (int w = 0; w < 4; ++w) {
+                acc += w < (tid >> 6) ? s_wsum[w] : 0;
+                nnz += s_wsum[w];
+            }
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                if (b0 + k < n) s_pos[b0 + k] = acc;
+                acc += f[k];
+            }
         }
         __syncthreads();
-        const int nnz = s_red[3];
         double* x64 = pl.x64 + d.v_off;
         double* x64lo = pl.x64lo + d.v_off;
         float* x32 = pl.x32 + d.v_off;

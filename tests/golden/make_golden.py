@@ -9,6 +9,7 @@ are skipped.
     python tests/golden/make_golden.py c5 --queries 15,14,13 --part b
     python tests/golden/make_golden.py c4wide wide
     python tests/golden/make_golden.py adia
+    python tests/golden/make_golden.py obs
 
 c4wide stores, in ``c4.wide.json``, queries of the batched workload's p = 5
 datasets with n > 512 (the kernels holding 10, 12 or 14 points per lane),
@@ -16,6 +17,9 @@ two per kernel class, from the two smallest datasets of each class; they lie
 above the subsample budget.  ``wide`` stores ``wide.json``: the samples of
 ``workloads.WIDE_CASES`` at the ends of those classes, keyed
 ``"<case>:<query>"`` (query 0 first for every case, then query 1).
+
+``obs`` stores ``adia_obs.json``: Algorithm 3's value and the exact count of
+every observation of the real-data stand-ins in ``OBS_SETS``.
 
 c5 is computed on its pre-map integer lattice: the mapped data is its exact
 integer affine image, and the depth does not change under such a map.
@@ -137,7 +141,39 @@ def run_adia(threads: int, exact_too):
             print("exact %s -> %d (%.1fs)" % (key, v, time.time() - t), flush=True)
 
 
+# Observation sets of the real-data stand-ins (every observation a query)
+# whose Algorithm 3 values are stored with the exact counts.
+OBS_SETS = [("scores", 3, 64), ("scores", 4, 64), ("returns", 3, 200), ("returns", 4, 200),
+            ("returns", 4, 500)]
+
+
+def run_obs(threads: int):
+    """adia_obs.json: for every observation of the sets in OBS_SETS, Algorithm
+    3's value (oracle_depth_adia) and the exact count (oracle_depth), keyed
+    "kind,p,n" -> list over the observations."""
+    path = os.path.join(HERE, "adia_obs.json")
+    obj = _load(path) or {"config": "adia_obs", "source": "oracle/td_oracle.cpp (oracle_depth_adia, oracle_depth)",
+                          "adia": {}, "exact": {}}
+    for kind, p, n in OBS_SETS:
+        key = "%s,%d,%d" % (kind, p, n)
+        X, Z = workloads.observations(kind, p, n)
+        if key not in obj["adia"]:
+            t = time.time()
+            v, _ = oracle.depth_adia(X, Z, threads=threads)
+            obj["adia"][key] = [int(x) for x in v]
+            _save(path, obj)
+            print("adia %s (%.1fs)" % (key, time.time() - t), flush=True)
+        if key not in obj["exact"]:
+            t = time.time()
+            v = oracle.depth_counts(X, Z, threads=threads)
+            obj["exact"][key] = [int(x) for x in v]
+            _save(path, obj)
+            print("exact %s (%.1fs)" % (key, time.time() - t), flush=True)
+
+
 def run(cfg: str, threads: int, queries=None, part=None):
+    if cfg == "obs":
+        return run_obs(threads)
     if cfg == "adia":
         return run_adia(threads, {"6,320,0.0", "5,640,0.0"})
     if cfg == "c4wide":

@@ -129,3 +129,36 @@ def test_adia_paper_grid_vs_stored_oracle(td, dev, key):
         rc = td.depth(to_dev(X, dev), to_dev(Z, dev)).cpu().numpy()
         assert int(rc[0]) == g["exact"][key]
         assert int(got[0]) >= g["exact"][key]
+
+
+def _obs_golden():
+    path = os.path.join(GOLD, "adia_obs.json")
+    if not os.path.exists(path):
+        return {"adia": {}, "exact": {}}
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("key", sorted(set(_obs_golden()["adia"]) & set(_obs_golden()["exact"])))
+def test_adia_every_observation_vs_stored_oracle(td, dev, key):
+    """Every observation of a real-data stand-in as a query (the paper's
+    real-data experiment): one call over all observations and one call per
+    observation both give the oracle's Algorithm 3 value for each of them,
+    never below the exact count that RCom returns."""
+    g = _obs_golden()
+    kind, p, n = key.split(",")
+    X, Z = workloads.observations(kind, int(p), int(n))
+    exp = np.array(g["adia"][key])
+    exact = np.array(g["exact"][key])
+    print("adia observations", key, flush=True)
+    got, st = run(td, dev, X, Z)
+    assert st["device_status"] == 0
+    assert np.array_equal(got, exp), (key, np.nonzero(got != exp)[0])
+    assert np.all(exp >= exact)
+    rc = td.depth(to_dev(X, dev), to_dev(Z, dev)).cpu().numpy()
+    assert np.array_equal(rc, exact)
+    # one call per observation: the differing ones and the first 16
+    idx = sorted(set(np.nonzero(exp != exact)[0].tolist()) | set(range(16)))
+    for q in idx:
+        one, _ = run(td, dev, X, Z[q])
+        assert int(one[0]) == int(exp[q]), (key, q, one, exp[q])
