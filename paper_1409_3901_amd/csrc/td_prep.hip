@@ -33,11 +33,21 @@ __global__ __launch_bounds__(256) void prep_kernel(Pools pl) {
     __shared__ int s_q;
     __shared__ double s_z[kMaxP];
     const int tid = threadIdx.x;
+    // block b takes query b first, then the shared counter the queries past
+    // the grid
+    bool first = true;
     while (true) {
-        if (tid == 0) s_q = (int)atomicAdd(&pl.ctr->prep_next, 1ull);
-        __syncthreads();
-        const int q = s_q;
-        __syncthreads();
+        int q;
+        if (first) {
+            q = (int)blockIdx.x;
+            first = false;
+        } else {
+            if ((int)gridDim.x >= pl.cp->num_queries) break;
+            if (tid == 0) s_q = (int)gridDim.x + (int)atomicAdd(&pl.ctr->prep_next, 1ull);
+            __syncthreads();
+            q = s_q;
+            __syncthreads();
+        }
         if (q >= pl.cp->num_queries) break;
         const QueryDesc d = pl.qd[q];
         const int n = d.n, p = d.p, M = d.M;

@@ -1068,6 +1068,10 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
     // address cost about 0.5 ms)
     const uint64_t nredo = REDO ? uni64(min((uint64_t)pl.ctr->redo_count[pl.cls], pl.redo_cap)) : 0;
     if (REDO && nredo == 0) return;
+    // first pass: block b takes item b first, then the shared counter hands
+    // out the items past the grid (no atomic at all when the grid covers the
+    // class)
+    bool first = true;
     while (true) {
         unsigned long long item = 0;
         uint64_t rstart = 0;
@@ -1096,8 +1100,14 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
                 rstop = rstart + kRedoUnit;
             }
         } else {
-            if (lane == 0) item = cbeg + atomicAdd(&pl.ctr->work_next[pl.cls], 1ull);
-            item = uni64(__shfl(item, 0, 64));
+            if (first) {
+                item = cbeg + blockIdx.x;
+                first = false;
+            } else {
+                if (cbeg + gridDim.x >= cend) break;
+                if (lane == 0) item = cbeg + gridDim.x + atomicAdd(&pl.ctr->work_next[pl.cls], 1ull);
+                item = uni64(__shfl(item, 0, 64));
+            }
             if (item >= cend) break;
         }
         const int q = uni(item_query(pl.qd, nq, item));

@@ -30,10 +30,18 @@ __global__ __launch_bounds__(64) void vertex_kernel(Pools pl) {
     const uint32_t chunk = pl.cp->cls_chunk[pl.cls];
     const int nq = pl.cp->num_queries;
     unsigned long long swept = 0;
+    // block b takes item b first, then the shared counter the items past the grid
+    bool first = true;
     while (true) {
         unsigned long long item = 0;
-        if (lane == 0) item = cbeg + atomicAdd(&pl.ctr->work_next[pl.cls], 1ull);
-        item = uni64(__shfl(item, 0, 64));
+        if (first) {
+            item = cbeg + blockIdx.x;
+            first = false;
+        } else {
+            if (cbeg + gridDim.x >= cend) break;
+            if (lane == 0) item = cbeg + gridDim.x + atomicAdd(&pl.ctr->work_next[pl.cls], 1ull);
+            item = uni64(__shfl(item, 0, 64));
+        }
         if (item >= cend) break;
         const int q = uni(item_query(pl.qd, nq, item));
         const QueryDesc d = pl.qd[q];
