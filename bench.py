@@ -296,7 +296,7 @@ def bench_p2(a, td, workloads, torch, np, dev):
                      "deferred_subsets": st["deferred_subsets"], "device_status": st["device_status"],
                      "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
                                   "frac": achieved / PEAK_VALU_TOPS, "traffic": None,
-                                  "kernel": "subset_kernel<2,16,%d>" % (3 if prec == "filtered" else 0),
+                                  "kernel": "subset_kernel<2,16,%d,false>" % (1 if prec == "filtered" else 0),
                                   "kernel_ms": sub_ms, "ops_per_launch": ops}}
     f = out["filtered"]
     print(json.dumps({"metric": "queries/s at p=2, n=1024 (one sweep per query)", "value": f["queries_per_s"],

@@ -86,9 +86,9 @@ typedef enum {
  * same exact counts. */
 typedef enum {
     TD_SWEEP_AUTO = 0,    /* counting sort into pseudo-angle buckets, exact
-                             order only where the sweep minimum may lie (full
-                             sort when that region is large, or for 1024
-                             points in a sweep) */
+                             order only where the sweep minimum may lie (the
+                             exact tier when that region is large); at p = 2,
+                             one sweep per query, the full sort */
     TD_SWEEP_BITONIC = 1  /* full bitonic sort of every sweep */
 } td_sweep;
 

@@ -304,6 +304,13 @@ int subset_tier(const td_options& o) {
     return o.sweep == TD_SWEEP_BITONIC ? td::kFilt : td::kFiltBucket;
 }
 
+// Tier of one class: at p = 2 the default sweep is the full sort.  A query
+// has a single sweep there, with no running minimum of other subsets to bound
+// it, so the bucket bounds rarely settle its minimum and most sweeps would be
+// walked by one lane (measured at n = 1024: 84% walked, 67 us against 38 us
+// for the full sort over 1,024 queries).
+int class_tier(int tier, int p) { return (tier == td::kFiltBucket && p == 2) ? td::kFilt : tier; }
+
 // Points per lane of the subset kernel for a sample of n points whose sort
 // width is M = 64 K.  The bucketed sweep needs no power-of-two width, so a
 // sample of 512 < n <= 896 at p <= 6 runs 10, 12 or 14 points per lane
@@ -334,6 +341,7 @@ int resident_blocks(DeviceCtx* dc, int tier, int p, int K) {
 
 struct ClassPlan {
     int p = 0, K = 0, M = 0;
+    int tier = 0;             // subset kernel tier of the class (class_tier)
     int Kk = 0;               // points per lane of the subset kernel
     int chunk = 0;            // subsets per work item
     Shape shape;
@@ -380,7 +388,8 @@ td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_optio
         if (pr.m == 0) continue;
         const int M = std::max(64, next_pow2((int)pr.n));
         const int K = M / 64;
-        const int Kk = kernel_k(tier, pr.p, pr.n, K);
+        const int ct = class_tier(tier, pr.p);
+        const int Kk = kernel_k(ct, pr.p, pr.n, K);
         int ib = 0;
         while ((1 << ib) < M) ++ib;
         int c = -1;
@@ -394,11 +403,12 @@ td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_optio
                 slot[key] = c;
                 ClassPlan cp;
                 cp.p = pr.p;
+                cp.tier = ct;
                 cp.K = K;
                 cp.Kk = Kk;
                 cp.M = M;
                 cp.chunk = o.chunk;
-                auto tt = dc->tuned.find(tune_key(tier, pr.p, Kk));
+                auto tt = dc->tuned.find(tune_key(ct, pr.p, Kk));
                 if (o.autotune && tt != dc->tuned.end()) {
                     cp.shape = tt->second;
                     if (cp.chunk == 0) cp.chunk = tt->second.chunk;
@@ -438,7 +448,7 @@ td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_optio
         // class with little work per query (p = 3, or few queries) still
         // spreads over every compute unit
         cp.chunk = 256;
-        const uint64_t want = 4ull * (uint64_t)dc->num_cu * (uint64_t)resident_blocks(dc, tier, cp.p, cp.Kk);
+        const uint64_t want = 4ull * (uint64_t)dc->num_cu * (uint64_t)resident_blocks(dc, cp.tier, cp.p, cp.Kk);
         while (cp.chunk > 64) {
             uint64_t it = 0;
             for (const QueryDesc& d : plan->qd)
@@ -483,7 +493,7 @@ td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_optio
     uint64_t soff = 0;
     for (ClassPlan& cp : plan->cls) {
         // default: every compute unit filled to the kernel's occupancy
-        int blocks = cp.shape.blocks > 0 ? cp.shape.blocks : dc->num_cu * resident_blocks(dc, tier, cp.p, cp.Kk);
+        int blocks = cp.shape.blocks > 0 ? cp.shape.blocks : dc->num_cu * resident_blocks(dc, cp.tier, cp.p, cp.Kk);
         if ((uint64_t)blocks > cp.items) blocks = (int)std::max<uint64_t>(1, cp.items);
         cp.shape.blocks = blocks;
         cp.xblocks = dc->num_cu * 4;
@@ -514,13 +524,13 @@ td_status enqueue(const Plan& plan, const Pools& base, const td_options& o, hipS
         Pools pl = base;
         pl.cls = (int)c;
         pl.wscratch_bytes = cp.scratch_per_block;
-        hipError_t e = tier == 0   ? td_launch_subset_plain(cp.p, cp.K, cp.shape.blocks, s, &pl)
-                       : tier == 1 ? td_launch_subset_filt(cp.p, cp.K, cp.shape.blocks, s, &pl)
-                                   : td_launch_subset_bucket(cp.p, cp.Kk, cp.shape.blocks, s, &pl);
+        hipError_t e = cp.tier == td::kPlain ? td_launch_subset_plain(cp.p, cp.K, cp.shape.blocks, s, &pl)
+                       : cp.tier == td::kFilt ? td_launch_subset_filt(cp.p, cp.K, cp.shape.blocks, s, &pl)
+                                              : td_launch_subset_bucket(cp.p, cp.Kk, cp.shape.blocks, s, &pl);
         if (e != hipSuccess) return TD_ERR_HIP;
         // the float64 pass of the bucketed sweep (p >= 3): the work items the
         // launch above handed over, usually none
-        if (tier == td::kFiltBucket && cp.p >= 3 &&
+        if (cp.tier == td::kFiltBucket && cp.p >= 3 &&
             td_launch_subset_bucket64(cp.p, cp.Kk, cp.shape.blocks, s, &pl) != hipSuccess)
             return TD_ERR_HIP;
     }
@@ -548,7 +558,8 @@ std::string graph_signature(const Plan& plan, const Pools& pl, const td_options&
                      std::to_string(pl.defer_cap) + "|" + std::to_string(pl.redo_cap) + "|" +
                      std::to_string(pl.sweep_mode) + "|" + std::to_string(pl.prune);
     for (const ClassPlan& cp : plan.cls) {
-        k += "|" + std::to_string(cp.p) + "," + std::to_string(cp.K) + "," + std::to_string(cp.Kk) + "," +
+        k += "|" + std::to_string(cp.p) + "," + std::to_string(cp.tier) + "," + std::to_string(cp.K) + "," +
+             std::to_string(cp.Kk) + "," +
              std::to_string(cp.shape.blocks) + "," + std::to_string(cp.scratch_per_block) + "," +
              std::to_string(cp.items > 0);
     }
@@ -1391,7 +1402,7 @@ td_status td_autotune(int32_t p, int64_t n, const td_options* base, void* stream
         DeviceCtx* dctx = nullptr;
         if (ensure_device(dev, &dctx) == TD_OK) num_cu = dctx->num_cu;
     }
-    const int tier = subset_tier(o);
+    const int tier = class_tier(subset_tier(o), p);
     const int K = kernel_k(tier, p, n, std::max(64, next_pow2((int)n)) / 64);
     float best = 1e30f;
     Shape bs;

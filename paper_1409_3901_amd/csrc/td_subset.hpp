@@ -18,7 +18,7 @@ namespace td {
 
 constexpr int kDefer = -2;
 constexpr int kSkip = -3;
-constexpr int kFallback = -4;   // bucketed sweep gave up: use the full sort
+constexpr int kFallback = -4;   // bucketed sweep gave up: the exact tier takes the subset
 constexpr int kNeed64 = -5;     // bucketed sweep needs the float64 basis
 constexpr uint64_t kRedoUnit = 1024;   // subsets per unit of the float64 pass
 constexpr int kBig = 0x7fffffff;
@@ -709,18 +709,6 @@ __device__ __forceinline__ int sweep_bucket(const float (&xr)[K][P], const SlotF
     }
 #pragma unroll
     for (int j = 0; j < NBL; ++j) hist[lane * NBL + j] = vzero();
-    if constexpr (P == 2) {
-        // 1024 points in one sweep: a bucket's crossing field (10 bits)
-        // overflows only if the bucket holds them all; that sweep goes to
-        // the full sort (the pos and neg fields hold up to 2047)
-        bool full = false;
-#pragma unroll
-        for (int j = 0; j < NBL; ++j) full = full || (int)((w[j] & 0x7ffu) + ((w[j] >> 11) & 0x7ffu)) >= 1024;
-        if (__any(full)) {
-            __syncthreads();
-            return kFallback;
-        }
-    }
     const int pre = incl - (int)tl;
     const int S0 = tot & 0x7ff;
     const int m = S0 + ((tot >> 11) & 0x7ff);
@@ -829,7 +817,7 @@ __device__ __forceinline__ int sweep_bucket(const float (&xr)[K][P], const SlotF
     for (int j = 0; j < NBL; ++j) hist[lane * NBL + j] = vzero();
     if (gtot > kListMax) {
         __syncthreads();
-        return kFallback;   // too many points to walk: the caller runs the full sort
+        return kFallback;   // too many points to walk: the caller defers the subset
     }
     {
         int k = gbase;
@@ -1029,9 +1017,10 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
     using Slot = typename SlotOf<P, TIER>::type;
     __shared__ Slot slots[64];
     constexpr bool BUCKET = TIER == kFiltBucket;
-    // side table of the full-sort sweep: the bitonic tier, and the bucketed
-    // kernels of p = 2, which sort in full what the buckets cannot finish
-    constexpr bool FULLSORT = TIER == kFilt || (BUCKET && P == 2);
+    // p = 2 (one sweep per query) always takes the full sort
+    static_assert(!(BUCKET && P == 2), "no bucketed sweep at p = 2");
+    // side table of the full-sort sweep
+    constexpr bool FULLSORT = TIER == kFilt;
     __shared__ uint16_t side[FULLSORT ? M : 1];
     __shared__ uint32_t hist[BUCKET ? BucketGeom<K>::HW : 1];
     __shared__ uint4 glist[BUCKET ? kListMax : 1];
@@ -1191,7 +1180,7 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
                     // the float64 basis is kept (in device scratch) only where a
                     // float64 re-check can read it: the full-sort sweeps and
                     // the float64 pass
-                    constexpr bool store64 = TIER == kFilt || P == 2 || REDO;
+                    constexpr bool store64 = TIER == kFilt || REDO;
 #pragma unroll
                     for (int c = 0; c < P; ++c) {
                         if (store64) {
@@ -1249,12 +1238,10 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
                         term = kDefer;
                     } else {
                         if constexpr (BUCKET) {
-                            // a walk gathers at most kListMax points, and a
-                            // bucket's crossing field counts at most 1023: at
-                            // p = 2 (one sweep per query) the full bitonic sort
-                            // takes the sweeps that exceed them, otherwise the
-                            // exact tier does (n <= 1024: at p >= 3 a sweep has
-                            // at most 1023 points)
+                            // a walk gathers at most kListMax points: the
+                            // exact tier takes the sweeps that exceed it (a
+                            // bucket's crossing field counts at most 1023, and
+                            // with n <= 1024 a sweep has at most 1023 points)
                             term = kFallback;
                             if (nnz - KS <= 1024) {
                                 const int ub = min(qbest, wbest);
@@ -1262,25 +1249,15 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
                                 term = sweep_bucket<P, K, REDO>(xf, SF, slots64[s], nnz, fc, hist, glist, sg, ub,
                                                                 rechecks, nwalked);
                                 if (term == kNeed64) {
-                                    if constexpr (P == 2) {
-                                        term = kFallback;   // the full sort has float64
-                                    } else {
-                                        // marked for the float64 pass; no branch
-                                        // out of the loop here (one makes the
-                                        // compiler turn the sweep's loops into
-                                        // exec-masked code: 11% at p = 5)
-                                        need |= 1ull << s;
-                                        continue;
-                                    }
+                                    // marked for the float64 pass; no branch
+                                    // out of the loop here (one makes the
+                                    // compiler turn the sweep's loops into
+                                    // exec-masked code: 11% at p = 5)
+                                    need |= 1ull << s;
+                                    continue;
                                 }
                             }
-                            if (term == kFallback) {
-                                if constexpr (P == 2)
-                                    term = sweep_filt<P, K>(xf, reinterpret_cast<const SlotFilt<P>&>(S), slots64[s],
-                                                            nnz, fc, side, sg, rechecks);
-                                else
-                                    term = kDefer;
-                            }
+                            if (term == kFallback) term = kDefer;
                         } else {
                             term = sweep_filt<P, K>(xf, reinterpret_cast<const SlotFilt<P>&>(S), slots64[s], nnz,
                                                     fc, side, sg, rechecks);
@@ -1304,7 +1281,7 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
                 wbest = min(wbest, term);
             }
             __syncthreads();
-            if constexpr (BUCKET && P > 2 && !REDO) {
+            if constexpr (BUCKET && !REDO) {
                 if (need) {
                     // hand the marked subsets and the rest of the item to the
                     // float64 pass; with its list full, the marked subsets go

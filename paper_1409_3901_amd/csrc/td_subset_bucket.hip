@@ -28,9 +28,9 @@ KernelFn pick_k(int K) {
     return nullptr;
 }
 
+// p >= 3: p = 2 runs the full-sort kernel
 KernelFn pick(int P, int K) {
     switch (P) {
-        case 2: return pick_k<2>(K);
         case 3: return pick_k<3>(K);
         case 4: return pick_k<4>(K);
         case 5: return pick_k<5>(K);

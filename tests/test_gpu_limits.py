@@ -1,8 +1,7 @@
 """The edges of the supported range against the oracle: the largest
 dimensions (p = 7, 8, where a subset has 5 or 6 members and the sort classes
 run at one or two waves per SIMD) and the largest sample (n = 1024, the full
-sort width, where p = 2 puts 1024 points in one sweep, more than the bucket
-words count, so every sweep goes to the exact tier)."""
+sort width, where p = 2 puts 1024 points in one sweep)."""
 import json
 import os
 

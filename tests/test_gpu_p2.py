@@ -1,8 +1,8 @@
 """p = 2: Algorithm 2 on its own (the index set of (p-2)-subsets holds only
 the empty set), one sweep of every query's n' points.  The p2 workload puts
 1023 points in the sweep of a sample-point query and 1024 in the others;
-the filtered tier sorts the latter in full (the bucket words count at most
-1023 points), and no p = 2 sweep may go to the exact tier."""
+the filtered tier sorts every p = 2 sweep in full, and no p = 2 sweep may go
+to the exact tier."""
 import json
 import os
 
