@@ -75,3 +75,20 @@ def test_adia_grid_covered():
         assert p - 2 <= g["candidates"][key] <= n
         if key in g["exact"]:
             assert g["exact"][key] <= g["adia"][key]
+
+
+def test_adia_observations_covered():
+    """adia_obs.json: for every observation of the real-data stand-ins, the
+    exact count and Algorithm 3's value, never below it, both within the
+    bound; every observation is a sample point, so n0 >= 1 and the depth
+    count is at least 1."""
+    with open(os.path.join(GOLD, "adia_obs.json")) as f:
+        g = json.load(f)
+    keys = {("scores", 3, 64), ("scores", 4, 64), ("returns", 3, 200), ("returns", 4, 200), ("returns", 4, 500)}
+    for kind, p, n in keys:
+        key = "%s,%d,%d" % (kind, p, n)
+        X, Z = workloads.observations(kind, p, n)
+        a, e = g["adia"][key], g["exact"][key]
+        assert len(a) == len(e) == n, key
+        for q in range(n):
+            assert 1 <= e[q] <= a[q] <= _bound(X, Z[q]), (key, q, e[q], a[q])
