@@ -1054,12 +1054,12 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
     // float64 pass: the handed-over items, counted by the first pass (which
     // has completed: the launches are stream-ordered); none, as a rule, and
     // then no block touches the shared work counter (4096 atomics on one
-    // address cost about 0.5 ms)
+    // address cost about 0.5 ms), nor when the grid covers every unit
     const uint64_t nredo = REDO ? uni64(min((uint64_t)pl.ctr->redo_count[pl.cls], pl.redo_cap)) : 0;
     if (REDO && nredo == 0) return;
-    // first pass: block b takes item b first, then the shared counter hands
-    // out the items past the grid (no atomic at all when the grid covers the
-    // class)
+    // block b takes item (float64 pass: unit) b first, then the shared
+    // counter hands out the ones past the grid (no atomic at all when the
+    // grid covers them)
     bool first = true;
     while (true) {
         unsigned long long item = 0;
@@ -1073,8 +1073,14 @@ __global__ __launch_bounds__(64, (min_waves<P, K, TIER>())) void subset_kernel(P
             // rest is left to a single wave
             const uint64_t upe = 1 + (chunk + kRedoUnit - 1) / kRedoUnit;
             unsigned long long u = 0;
-            if (lane == 0) u = atomicAdd(&pl.ctr->redo_next[pl.cls], 1ull);
-            u = uni64(__shfl(u, 0, 64));
+            if (first) {
+                u = blockIdx.x;
+                first = false;
+            } else {
+                if ((uint64_t)gridDim.x >= nredo * upe) break;
+                if (lane == 0) u = gridDim.x + atomicAdd(&pl.ctr->redo_next[pl.cls], 1ull);
+                u = uni64(__shfl(u, 0, 64));
+            }
             const uint64_t e = u / upe;
             if (e >= nredo) break;
             const uint64_t k = u - e * upe;
