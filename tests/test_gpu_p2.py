@@ -28,6 +28,9 @@ def test_p2_workload_vs_stored_oracle(td, dev, prec):
     assert st["device_status"] == 0
     if prec != "plain":
         assert st["deferred_subsets"] == 0, st
+        # every p = 2 sweep takes the full sort: none is walked
+        assert st["walked_sweeps"] == 0, st
+        assert st["subsets_swept"] == Z.shape[0], st
     assert np.array_equal(got, exp), int(np.sum(got != exp))
 
 
