@@ -587,6 +587,140 @@ __device__ __forceinline__ uint32_t vzero() {
     return z;
 }
 
+// Inclusive sum over the lanes of the same segment (segments are contiguous
+// runs of lanes with equal `seg`): the rare walk's scans.
+__device__ __forceinline__ int seg_incl_sum(int v, int seg) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int vv = __shfl_up(v, d, 64);
+        const int gg = __shfl_up(seg, d, 64);
+        if (lane >= d && gg == seg) v += vv;
+    }
+    return v;
+}
+
+// Exclusive prefix maximum over the lanes (lane 0 reads `id`).
+__device__ __forceinline__ int excl_max_shfl(int v, int id) {
+    const int lane = lane_id();
+    int m = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int vv = __shfl_up(m, d, 64);
+        if (lane >= d) m = max(m, vv);
+    }
+    const int prev = __shfl_up(m, 1, 64);
+    return lane == 0 ? id : prev;
+}
+
+// The walk of the first pass (no float64 code), over the gathered points
+// sorted by the lower ends of their key intervals (at most 128: entry e in
+// lane e % 64 of half e / 64).  The same clusters as the one-lane walk of
+// the float64 pass, decided in parallel: an entry starts a cluster when it
+// starts a run or its lower end lies above every upper end before it in its
+// run; the state after an entry is its run's left-boundary state plus the
+// +1 / -1 of the entries of the run up to it.  The states after the clusters
+// hold for any order inside the clusters, and their minimum `best` bounds
+// every cluster's inner states from above, so a cluster with both fold
+// signs needs an exact inner order only if its states could go below
+// min(U, ubound, best).  Returns min(U, best), or kNeed64 (kDefer for a
+// cluster above kClusterMax) when some cluster needs its inner order.
+__device__ __forceinline__ int walk_lean(const uint4* list, int gtot, int m, int U, int ubound) {
+    const int lane = lane_id();
+    constexpr int kNoRun = 0x7fff;
+    int run[2], srun[2], comb[2], delta[2], pos[2];
+    uint32_t lo[2];
+    bool in[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int e = lane + 64 * h;
+        in[h] = e < gtot;
+        const uint4 v = in[h] ? list[e] : make_uint4(0u, 0u, 0u, 0u);
+        run[h] = in[h] ? (int)(v.z >> 11) : kNoRun;
+        srun[h] = (int)(v.z & 0x7ffu);
+        lo[h] = v.x;
+        const uint32_t hi = v.x + (v.y & 0x7fffffffu);
+        pos[h] = (in[h] && !(v.y & kAuxNeg)) ? 1 : 0;
+        delta[h] = in[h] ? (pos[h] ? -1 : 1) : 0;
+        // run and upper end in one key that grows along the sorted list
+        // (runs in increasing order; upper ends below 2^24 in the binade)
+        comb[h] = in[h] ? (run[h] << 23) | (int)(hi - kKeyBias) : -1;
+    }
+    // cluster starts
+    bool start[2];
+    {
+        const int m0 = __builtin_amdgcn_readlane(wave_incl_max_dpp(comb[0]), 63);
+        const int ex0 = excl_max_shfl(comb[0], -1);
+        const int ex1 = max(excl_max_shfl(comb[1], -1), m0);
+        const int ex[2] = {ex0, ex1};
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            start[h] = in[h] && (ex[h] < 0 || (ex[h] >> 23) != run[h] ||
+                                 lo[h] > (uint32_t)(ex[h] & 0x7fffff) + kKeyBias);
+    }
+    // cluster ids (global count of starts up to the entry)
+    int cid[2];
+    cid[0] = wave_incl_sum_dpp(start[0] ? 1 : 0);
+    cid[1] = __builtin_amdgcn_readlane(cid[0], 63) + wave_incl_sum_dpp(start[1] ? 1 : 0);
+    if (!in[0]) cid[0] = -1 - lane;
+    if (!in[1]) cid[1] = -1000 - lane;
+    // states after the entries (sums over the run), and counts and positive
+    // points of the cluster up to the entry; the second half continues the
+    // segment of the first half's last entry
+    int send[2], cnt[2], np[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        send[h] = seg_incl_sum(delta[h], run[h]);
+        cnt[h] = seg_incl_sum(in[h] ? 1 : 0, cid[h]);
+        np[h] = seg_incl_sum(pos[h], cid[h]);
+    }
+    {
+        const int r63 = __builtin_amdgcn_readlane(run[0], 63);
+        const int s63 = __builtin_amdgcn_readlane(send[0], 63);
+        const int c63 = __builtin_amdgcn_readlane(cid[0], 63);
+        const int n63 = __builtin_amdgcn_readlane(cnt[0], 63);
+        const int p63 = __builtin_amdgcn_readlane(np[0], 63);
+        if (in[1] && run[1] == r63) send[1] += s63;
+        if (in[1] && cid[1] == c63) {
+            cnt[1] += n63;
+            np[1] += p63;
+        }
+    }
+    // cluster ends: the last entry, or one followed by a start
+    bool end[2];
+    {
+        const int sb0 = __builtin_amdgcn_readlane(start[1] ? 1 : 0, 0);
+        const int nx0 = __shfl_down(start[0] ? 1 : 0, 1, 64);
+        const int nx1 = __shfl_down(start[1] ? 1 : 0, 1, 64);
+        end[0] = in[0] && (lane + 1 == gtot || (lane < 63 ? nx0 != 0 : sb0 != 0));
+        end[1] = in[1] && (lane + 65 == gtot || (lane < 63 && nx1 != 0));
+    }
+    int best = kBig;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        send[h] += srun[h];
+        if (end[h]) best = min(best, fside(send[h], m));
+    }
+    best = wave_min(best);
+    const int bound = min(min(U, ubound), best);
+    bool need = false, big = false;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (!end[h]) continue;
+        const int c = cnt[h], npc = np[h];
+        if (npc == 0 || npc == c) continue;   // one fold sign: any order
+        const int s0 = send[h] - (c - 2 * npc);   // state before the cluster
+        const int dip = min(s0 - npc, m - (s0 + (c - npc)));
+        if (dip < bound) {
+            need = true;
+            big = big || c > kClusterMax;
+        }
+    }
+    if (__any(big)) return kDefer;
+    if (__any(need)) return kNeed64;
+    return min(U, best);
+}
+
 // F64 = false: the sweep without any float64 code (its registers cost the
 // kernel's loop about 12% at p = 5 even where it never runs): where float64
 // is needed it returns kNeed64.  F64 = true: the same sweep with the float64
@@ -851,6 +985,11 @@ __device__ __forceinline__ int sweep_bucket(const float (&xr)[K][P], const SlotF
         if (j0 < gtot) list[r0] = v0;
         if (j1 < gtot) list[r1] = v1;
         __syncthreads();
+    }
+    if constexpr (!F64) {
+        const int term = walk_lean(list, gtot, m, U, ubound);
+        __syncthreads();
+        return term;
     }
     int best = kBig, defer = 0;
     if (lane == 0) {
