@@ -14,6 +14,29 @@ __global__ void init_kernel(Counters* ctr) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0ull;
 }
 
+// The thread's part of the bound from the directions +-x_j: for its rows j,
+// the closed-side counts of u = s_x[j] over all nnz rows (p = P, rows of P
+// floats in LDS), a count taken whenever the product is within e of the side.
+template <int P>
+__device__ int dir_bound(const float* s_x, int nnz, int tid, float e) {
+    int ub = 0x7fffffff;
+    for (int j = tid; j < nnz; j += blockDim.x) {
+        float u[P];
+#pragma unroll
+        for (int c = 0; c < P; ++c) u[c] = s_x[j * P + c];
+        int le = 0, ge = 0;
+        for (int i = 0; i < nnz; ++i) {
+            float dot = 0.0f;
+#pragma unroll
+            for (int c = 0; c < P; ++c) dot = fmaf(u[c], s_x[i * P + c], dot);
+            le += dot <= e ? 1 : 0;
+            ge += dot >= -e ? 1 : 0;
+        }
+        ub = min(ub, min(le, ge));
+    }
+    return ub;
+}
+
 // One block of 256 threads per query (persistent over queries).  Shift to the
 // query (Section 2: x_i = X_i - z), drop the observations equal to it (they
 // lie on every hyperplane through z and add n0 to every count), and store
@@ -209,20 +232,13 @@ __global__ __launch_bounds__(256) void prep_kernel(Pools pl) {
             for (int k = tid; k < nnz * p; k += blockDim.x) s_x[k] = x32[k];
             __syncthreads();
             const float e = ((float)p + 4.0f) * kU32;
-            for (int j = tid; j < nnz; j += blockDim.x) {
-                float u[kMaxP];
-#pragma unroll
-                for (int c = 0; c < kMaxP; ++c) u[c] = c < p ? s_x[j * p + c] : 0.0f;
-                int le = 0, ge = 0;
-                for (int i = 0; i < nnz; ++i) {
-                    float dot = 0.0f;
-#pragma unroll
-                    for (int c = 0; c < kMaxP; ++c)
-                        if (c < p) dot = fmaf(u[c], s_x[i * p + c], dot);
-                    le += dot <= e ? 1 : 0;
-                    ge += dot >= -e ? 1 : 0;
-                }
-                ub = min(ub, min(le, ge));
+            switch (p) {
+                case 3: ub = dir_bound<3>(s_x, nnz, tid, e); break;
+                case 4: ub = dir_bound<4>(s_x, nnz, tid, e); break;
+                case 5: ub = dir_bound<5>(s_x, nnz, tid, e); break;
+                case 6: ub = dir_bound<6>(s_x, nnz, tid, e); break;
+                case 7: ub = dir_bound<7>(s_x, nnz, tid, e); break;
+                default: ub = dir_bound<8>(s_x, nnz, tid, e); break;
             }
             ub = wave_min(ub);
             __syncthreads();
