@@ -665,6 +665,11 @@ def bench_every_point(td, workloads, torch, np, dev):
                      "gpu_ms_per_observation": best / n, "sweeps_per_s": covered / (best / 1e3),
                      "pruned_subsets": st["pruned_subsets"], "device_status": st["device_status"],
                      "depth_min": int(counts.min()), "depth_max": int(counts.max()),
+                     # the deepest observations (the sample's Tukey median among
+                     # its own points) and the depth levels of the paper's
+                     # figure of sorted depths: observations per depth count
+                     "deepest_observations": [int(i) for i in np.nonzero(counts == counts.max())[0]],
+                     "observations_per_depth": {int(k): int(v) for k, v in zip(*np.unique(counts, return_counts=True))},
                      "adia_ms_min": min(adia_ms), "adia_ms_mean": sum(adia_ms) / n, "adia_ms_max": max(adia_ms),
                      "adia_equal_to_rcom": "%d of %d" % (adia_agree, n),
                      "adia_ms_all_observations_one_call": adia_all,
