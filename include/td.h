@@ -186,6 +186,13 @@ typedef struct {
                                     finished by its float64 pass: from the
                                     first sweep of the item that needed the
                                     float64 re-check or re-order on */
+    uint64_t adia_rcom_queries;  /* TD_METHOD_ADIA: queries that Algorithm 1
+                                    answered instead: n <= 2p or p < 3 (as
+                                    Section 4 advises), no seed subset in
+                                    Step 2(c), an evaluation with more than 32
+                                    points next to its minimising states (the
+                                    set T of Step 4(a)(ii)), or a descent of
+                                    more than 4 C(n, p-2) + 4096 evaluations */
 } td_stats;
 
 /* One independent depth problem of a batch (pointers as for td_depth). */

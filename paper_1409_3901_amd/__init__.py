@@ -68,6 +68,7 @@ class Stats(ctypes.Structure):
         ("adia_evaluations", ctypes.c_uint64),
         ("adia_candidates", ctypes.c_uint64),
         ("f64_items", ctypes.c_uint64),
+        ("adia_rcom_queries", ctypes.c_uint64),
     ]
 
 

@@ -155,6 +155,7 @@ struct DeviceCtx {
 struct LastCall {
     uint64_t adia_evaluations = 0;  // Algorithm 3: subsets evaluated in Steps 2-4
     uint64_t adia_candidates = 0;   // and candidate points of Step 5 (summed)
+    uint64_t adia_rcom = 0;         // and queries Algorithm 1 answered
     Workspace* ws = nullptr;        // null after an allocation-free call
     int device = -1;
     const Counters* ctr = nullptr;  // device counters and query states of the call
@@ -685,6 +686,7 @@ td_status run(const Problem* probs, int num, const td_options& o, hipStream_t st
 
     g_last.adia_evaluations = 0;
     g_last.adia_candidates = 0;
+    g_last.adia_rcom = 0;
     g_last.ws = w;
     g_last.device = w->device;
     g_last.ctr = w->ctr;
@@ -769,7 +771,11 @@ std::vector<int> adia_points(const td::AdiaRes& r) {
 
 td_status run_adia(const Problem& pr, const td_options& o, hipStream_t stream) {
     // the paper uses Algorithm 1 for n <= 2p; p < 3 has no descent
-    if (pr.p < 3 || pr.n <= 2 * pr.p) return run(&pr, 1, o, stream, false);
+    if (pr.p < 3 || pr.n <= 2 * pr.p) {
+        const td_status s1 = run(&pr, 1, o, stream, false);
+        g_last.adia_rcom = (uint64_t)pr.m;
+        return s1;
+    }
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return TD_ERR_NO_DEVICE;
     DeviceCtx* dc = nullptr;
@@ -828,7 +834,9 @@ td_status run_adia(const Problem& pr, const td_options& o, hipStream_t stream) {
     for (size_t e = 0; e < jobs.size(); ++e) {
         QueryRun& qr = R[(size_t)jq[e]];
         std::vector<int> I(jobs[e].idx, jobs[e].idx + ks);
-        if (res[e].term < 0) continue;
+        // no seed, or more points next to a minimising state than an
+        // evaluation lists: the query takes Algorithm 1
+        if (res[e].term < 0 || res[e].tcount > td::kAdiaTMax) continue;
         int h = -1;
         for (int v : adia_points(res[e]))
             if (std::find(I.begin(), I.end(), v) == I.end()) { h = v; break; }
@@ -883,11 +891,20 @@ td_status run_adia(const Problem& pr, const td_options& o, hipStream_t stream) {
             for (const std::vector<int>& F : popped[(size_t)q]) {
                 const size_t base = e0;
                 e0 += (size_t)ks + 1;
-                if (!qr.Q.count(F)) continue;   // deleted by an earlier node: not popped
+                // deleted by an earlier node (not popped), or the query left
+                // the descent
+                if (qr.mode != kAdia || !qr.Q.count(F)) continue;
                 qr.evals += (uint64_t)ks + 1;   // the descent's own work (not the speculation)
+                bool listed = true;
                 for (int r = 0; r < ks + 1; ++r) {
                     const td::AdiaRes& rr = res[base + (size_t)r];
                     if (rr.term < 0) continue;
+                    // the set T of Step 4(a)(ii) is longer than an evaluation
+                    // lists: the query takes Algorithm 1
+                    if (rr.tcount > td::kAdiaTMax) {
+                        listed = false;
+                        break;
+                    }
                     std::vector<int> J(jobs[base + (size_t)r].idx, jobs[base + (size_t)r].idx + ks);
                     for (int v : adia_points(rr)) {
                         if (std::find(F.begin(), F.end(), v) != F.end()) continue;
@@ -904,6 +921,10 @@ td_status run_adia(const Problem& pr, const td_options& o, hipStream_t stream) {
                         qr.bestJ = J;
                         break;
                     }
+                }
+                if (!listed) {
+                    qr.mode = kRcom;
+                    continue;
                 }
                 for (auto it = qr.Q.begin(); it != qr.Q.end();) {
                     if (it->second > qr.d0) it = qr.Q.erase(it); else ++it;
@@ -963,6 +984,7 @@ td_status run_adia(const Problem& pr, const td_options& o, hipStream_t stream) {
     st = run(&pr, 1, po, stream, false, &patch);
     g_last.adia_evaluations = evaluations;
     g_last.adia_candidates = cands;
+    for (int q = 0; q < nq; ++q) g_last.adia_rcom += R[(size_t)q].mode == kRcom ? 1 : 0;
     return st;
 }
 
@@ -1006,6 +1028,7 @@ td_status run_vertex(const Problem& pr, const td_options& o, hipStream_t stream)
     if ((st = setup_call(dc, w, plan, po, stream, &pl)) != TD_OK) return st;
     g_last.adia_evaluations = 0;
     g_last.adia_candidates = 0;
+    g_last.adia_rcom = 0;
     g_last.ws = w;
     g_last.device = w->device;
     g_last.ctr = w->ctr;
@@ -1221,6 +1244,7 @@ td_status run_noalloc(const Problem& pr, const td_options& o, hipStream_t stream
 
     g_last.adia_evaluations = 0;
     g_last.adia_candidates = 0;
+    g_last.adia_rcom = 0;
     g_last.ws = nullptr;
     g_last.device = dev;
     g_last.ctr = pl.ctr;
@@ -1339,6 +1363,7 @@ td_status td_get_stats(td_stats* out) {
     out->exact_subsets = c.exact_done;
     out->adia_evaluations = g_last.adia_evaluations;
     out->adia_candidates = g_last.adia_candidates;
+    out->adia_rcom_queries = g_last.adia_rcom;
     for (int k = 0; k < td::kMaxClasses; ++k) out->f64_items += std::min<uint64_t>(c.redo_count[k], g_last.redo_cap);
     std::vector<QueryState> qs(g_last.nq);
     if (g_last.nq > 0) HIPCHK(hipMemcpy(qs.data(), g_last.qs, qs.size() * sizeof(QueryState), hipMemcpyDeviceToHost));

@@ -19,7 +19,7 @@ int main(void) {
     F(td_stats, device_status); F(td_stats, prep_ms); F(td_stats, subset_ms); F(td_stats, exact_ms);
     F(td_stats, finalize_ms); F(td_stats, total_ms); F(td_stats, walked_sweeps); F(td_stats, pruned_subsets);
     F(td_stats, exact_subsets); F(td_stats, adia_evaluations); F(td_stats, adia_candidates);
-    F(td_stats, f64_items);
+    F(td_stats, f64_items); F(td_stats, adia_rcom_queries);
     printf("td_problem %zu\n", sizeof(td_problem));
     F(td_problem, X); F(td_problem, n); F(td_problem, p); F(td_problem, Z); F(td_problem, m);
     F(td_problem, counts);

@@ -89,6 +89,35 @@ def test_adia_small_samples_and_p2_use_algorithm_1(td, dev):
         got, st = run(td, dev, X, Z)
         assert np.array_equal(got, oracle.depth_counts(X, Z))
         assert st["adia_evaluations"] == 0
+        assert st["adia_rcom_queries"] == 3
+
+
+def test_adia_long_tie_groups_take_algorithm_1(td, dev):
+    """Two rays of 45 and 40 points from the query among 50 general points
+    (p = 3): the first evaluation meets an exact tie group longer than an
+    evaluation lists (32 points next to its minimising states), so
+    Algorithm 1 answers the query (counted in adia_rcom_queries) and the
+    count is the exact one.  The descent of a general-position query in the
+    same call is unaffected."""
+    rng = np.random.default_rng(0)
+    p = 3
+    d = rng.standard_normal(p)
+    G = rng.standard_normal((50, p))
+    ray = np.outer(np.linspace(0.5, 3.0, 45), d)
+    rng.standard_normal((1, p))
+    ray2 = np.outer(np.linspace(0.5, 3.0, 40), -d + 0.3 * rng.standard_normal(p))
+    X = np.vstack([G, ray, ray2])
+    Z = np.zeros((1, p))
+    got, st = run(td, dev, X, Z)
+    assert st["device_status"] == 0
+    assert st["adia_rcom_queries"] == 1, st
+    assert int(got[0]) == int(oracle.depth_counts(X, Z)[0])
+    # with a general-position query beside it, only the tied one falls back
+    Z2 = np.vstack([Z, 0.2 * rng.standard_normal((1, p))])
+    got2, st2 = run(td, dev, X, Z2)
+    assert st2["adia_rcom_queries"] >= 1
+    assert int(got2[0]) == int(got[0])
+    assert int(got2[1]) >= int(oracle.depth_counts(X, Z2[1:])[0])
 
 
 def test_adia_unsupported_entry_points(td, dev):
