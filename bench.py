@@ -570,6 +570,7 @@ def bench_paper_grid(td, workloads, torch, np, dev):
                     if meth == "adia":
                         row["adia_evaluations"] = st["adia_evaluations"]
                         row["adia_candidates"] = st["adia_candidates"]
+                        row["adia_answered_by_rcom"] = st["adia_rcom_queries"]
                 row["counts_agree"] = row["rcom_count"] == row["adia_count"]
                 # the vertex-form check (Proposition 1 with r = p - 1, the
                 # critical-direction route), O(n^p): one timed call where the
