@@ -61,9 +61,62 @@ __device__ __forceinline__ int dot_sign64(const double* x64, int p, int a, int b
     return s > bound ? 1 : (s < -bound ? -1 : 0);
 }
 
-// Step 2, one block per query.  (a) u_min: over j and the sign (x_j before
-// -x_j), the fewest points with u . x_i <= 0, smallest j first; (b) the p - 2
-// points with the smallest nonnegative u_min . x_i (by value, then index).
+// Step 2(a) is split over blocks: the keys start at the largest value, then
+// block (q, s) takes the directions x_j, j in [64 s, 64 s + 64), of query q;
+// its thread (jj, h) counts the points i = h, h + 4, ... on either closed
+// side of x_{64 s + jj}, the four partial counts are added in LDS, and the
+// smallest key count * 2n' + 2j + (sign < 0) of the block goes to
+// seeds[q].best by an atomic minimum (the keys are nonnegative, so the
+// minimum over the blocks is the minimum over every direction).
+__global__ void adia_best_init_kernel(AdiaSeed* seeds, int nq) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nq) seeds[q].best = ~0ull;
+}
+
+constexpr int kSeedSlices = kMaxN / 64;
+
+__global__ __launch_bounds__(256) void adia_dirs_kernel(Pools pl, AdiaSeed* seeds) {
+    __shared__ int s_cp[4][64];
+    __shared__ int s_cn[4][64];
+    __shared__ long long s_red[4];
+    const int q = blockIdx.x / kSeedSlices;
+    const int sl = blockIdx.x % kSeedSlices;
+    if (q >= pl.cp->num_queries) return;
+    const int nnz = pl.qs[q].nnz;
+    const int p = pl.qd[q].p;
+    if (nnz <= 0 || p < 3 || sl * 64 >= nnz) return;
+    const double* x64 = pl.x64 + pl.qd[q].v_off;
+    const int tid = threadIdx.x;
+    const int jj = tid & 63, h = tid >> 6;
+    const int j = sl * 64 + jj;
+    int cp = 0, cn = 0;
+    if (j < nnz) {
+        for (int i = h; i < nnz; i += 4) {
+            double v;
+            const int sg = dot_sign64(x64, p, j, i, v);
+            cp += sg <= 0 ? 1 : 0;
+            cn += sg >= 0 ? 1 : 0;
+        }
+    }
+    s_cp[h][jj] = cp;
+    s_cn[h][jj] = cn;
+    __syncthreads();
+    long long key = 0x7fffffffffffffffll;
+    if (h == 0 && j < nnz) {
+        const int tp = s_cp[0][jj] + s_cp[1][jj] + s_cp[2][jj] + s_cp[3][jj];
+        const int tn = s_cn[0][jj] + s_cn[1][jj] + s_cn[2][jj] + s_cn[3][jj];
+        const long long kp = (long long)tp * (2ll * nnz) + 2ll * j;
+        const long long kn = (long long)tn * (2ll * nnz) + 2ll * j + 1;
+        key = kp < kn ? kp : kn;
+    }
+    key = block_min_ll(key, s_red);
+    if (tid == 0) atomicMin(&seeds[q].best, (unsigned long long)key);
+}
+
+// Step 2, one block per query, after adia_dirs_kernel.  (a) u_min: over j
+// and the sign (x_j before -x_j), the fewest points with u . x_i <= 0,
+// smallest j first (the key of seeds[q].best); (b) the p - 2 points with the
+// smallest nonnegative u_min . x_i (by value, then index).
 __global__ __launch_bounds__(256) void adia_seed_kernel(Pools pl, AdiaSeed* seeds) {
     __shared__ double s_pr[kMaxN];
     __shared__ long long s_red[4];
@@ -80,26 +133,14 @@ __global__ __launch_bounds__(256) void adia_seed_kernel(Pools pl, AdiaSeed* seed
     out.kneg = 0;
     out.ok = 0;
     for (int c = 0; c < kMaxP - 2; ++c) out.idx[c] = -1;
+    out.best = ~0ull;
     if (nnz <= 0 || p < 3) {
         if (tid == 0) seeds[q] = out;
         return;
     }
-    // (a) key = count * 2n + 2j + (sign < 0): the smallest key wins
-    long long best = 0x7fffffffffffffffll;
-    for (int j = tid; j < nnz; j += blockDim.x) {
-        int cp = 0, cn = 0;
-        for (int i = 0; i < nnz; ++i) {
-            double v;
-            const int sg = dot_sign64(x64, p, j, i, v);
-            cp += sg <= 0 ? 1 : 0;
-            cn += sg >= 0 ? 1 : 0;
-        }
-        const long long kp = (long long)cp * (2ll * nnz) + 2ll * j;
-        const long long kn = (long long)cn * (2ll * nnz) + 2ll * j + 1;
-        best = kp < best ? kp : best;
-        best = kn < best ? kn : best;
-    }
-    best = block_min_ll(best, s_red);
+    // (a) key = count * 2n + 2j + (sign < 0): the smallest key, found by
+    // adia_dirs_kernel (nnz > 0: at least one direction)
+    const long long best = (long long)seeds[q].best;
     const int r = (int)(best % (2ll * nnz));
     const int bj = r >> 1;
     const double sgn = (r & 1) ? -1.0 : 1.0;
@@ -428,6 +469,8 @@ EvalFn pick_eval(int P, int K) {
 }  // namespace
 
 extern "C" hipError_t td_launch_adia_seed(const td::Pools* pl, int nq, td::AdiaSeed* seeds, hipStream_t s) {
+    hipLaunchKernelGGL(td::adia_best_init_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, seeds, nq);
+    hipLaunchKernelGGL(td::adia_dirs_kernel, dim3((unsigned)nq * td::kSeedSlices), dim3(256), 0, s, *pl, seeds);
     hipLaunchKernelGGL(td::adia_seed_kernel, dim3(nq), dim3(256), 0, s, *pl, seeds);
     return hipGetLastError();
 }

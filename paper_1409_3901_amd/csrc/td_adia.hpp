@@ -12,11 +12,14 @@ namespace td {
 constexpr int kAdiaTMax = 32;
 
 // Step 2 of one query: kneg = points strictly below u_min (0: the depth is
-// n0), ok = a seed subset was found, idx = the seed subset.
+// n0), ok = a seed subset was found, idx = the seed subset; best = the
+// smallest key count * 2n' + 2j + (sign < 0) of Step 2(a) over the directions
+// +-x_j (device side only).
 struct AdiaSeed {
     int32_t kneg;
     int32_t ok;
     int32_t idx[kMaxP - 2];
+    unsigned long long best;
 };
 
 // One (p-2)-subset to evaluate: query and point indices (ascending).
