@@ -278,8 +278,12 @@ struct ExactScratch {
     int hsig[kExactClusterMax];
 };
 
+// Two waves per SIMD: the kernel is latency-bound (big-integer predicates,
+// one lane's walks), and a second wave hides it (c5, 2.3 million deferred
+// subsets: 347 -> 235 ms; four waves per SIMD gain little more and slow the
+// single subsets of small calls).
 template <int P, int K>
-__global__ __launch_bounds__(64) void exact_kernel(Pools pl) {
+__global__ __launch_bounds__(64, 2) void exact_kernel(Pools pl) {
     constexpr int KS = P - 2;
     constexpr int M = 64 * K;
     constexpr int NF = XS<P>::NF;

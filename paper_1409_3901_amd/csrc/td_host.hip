@@ -497,7 +497,7 @@ td_status make_plan(DeviceCtx* dc, const Problem* probs, int num, const td_optio
         int blocks = cp.shape.blocks > 0 ? cp.shape.blocks : dc->num_cu * resident_blocks(dc, cp.tier, cp.p, cp.Kk);
         if ((uint64_t)blocks > cp.items) blocks = (int)std::max<uint64_t>(1, cp.items);
         cp.shape.blocks = blocks;
-        cp.xblocks = dc->num_cu * 4;
+        cp.xblocks = dc->num_cu * 8;   // the exact kernel: 2 waves per SIMD
         uint64_t per = std::max<uint64_t>(td::wave_scratch_bytes(cp.M), td_exact_scratch_bytes(cp.p));
         per = (per + 255) & ~(uint64_t)255;
         cp.scratch_per_block = per;
